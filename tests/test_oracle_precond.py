@@ -1,0 +1,140 @@
+"""Pins of the oracle's block-acoustic preconditioner and FGMRES (CPU only):
+Theorem 3.1 on small heterogeneous grids, the exact one-iteration solve for
+constant media, the block form of eq. precond_system and the iteration
+counts the paper prints (Tables scalability_linear and 2Dlinear)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.analysis import Z_matrix, commutator, distributed_matrix
+from oracle.elastic import ElasticSystem
+from oracle.fgmres import fgmres
+from oracle.precond import BlockAcoustic
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def hetero(n, seed=0, omega=1.2, abc=2):
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(n))
+    vp = rng.uniform(2.0, 3.5, shape)
+    vs = vp * rng.uniform(0.35, 0.55, shape)
+    rho = rng.uniform(1.0, 2.0, shape)
+    return ElasticSystem(n, (1.0,) * len(n), vp, vs, rho, omega=omega,
+                         abc_width=abc, abc_sides=W.ABC_ALL[len(n)])
+
+
+def precond_matrix(M, ndof):
+    """Columns of the preconditioner map r -> z, applied to the identity."""
+    cols = [M.apply(np.eye(ndof, 1, -j).ravel().astype(np.complex128))
+            for j in range(ndof)]
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("n", [(12, 10), (4, 4, 3)])
+def test_theorem_3_1(n):
+    """T = I - (P^{-1} D_L) H has a null space of dimension n_u (the size of
+    A) and spec(T) minus {0} equals spec(Z) minus {0}, Z = Xi A^-1 B^T H_p^-1
+    (Theorem 3.1).  The preconditioner is the oracle's own application
+    routine with exact block solves, read off column by column."""
+    s = hetero(n, 1)
+    M = BlockAcoustic(s, alpha=0.0, solver="exact")
+    Mmat = precond_matrix(M, s.ndof)
+    T = np.eye(s.ndof) - Mmat @ s.H().toarray()
+    sv = np.linalg.svd(T, compute_uv=False)
+    nullity = int(np.sum(sv < 1e-9 * sv[0]))
+    assert nullity == s.nu_total
+    eT = np.linalg.eigvals(T)
+    eZ = np.linalg.eigvals(Z_matrix(s))
+    big = lambda e: np.sort_complex(e[np.abs(e) > 1e-8])
+    eT, eZ = big(eT), big(eZ)
+    assert eT.shape == eZ.shape
+    # match each eigenvalue of T to its nearest of Z
+    d = np.abs(eT[:, None] - eZ[None, :]).min(axis=1)
+    assert d.max() <= 1e-8 * max(1.0, np.abs(eZ).max())
+    # rho(T) = rho(Z)
+    assert abs(np.abs(eT).max() - np.abs(eZ).max()) <= 1e-9
+
+
+def test_block_form_of_preconditioned_distributed_system():
+    """P^{-1} K = [I - A^-1 B^T H_p^-1 Xi, 0; H_p^-1 Xi, I]
+    (eq. precond_system), with P^{-1} D_L read off the oracle routine."""
+    n = (8, 6)
+    s = hetero(n, 2)
+    M = BlockAcoustic(s, alpha=0.0, solver="exact")
+    Mmat = precond_matrix(M, s.ndof)
+    K, DL = distributed_matrix(s)
+    # M = P^{-1} D_L, so P^{-1} K = P^{-1} D_L H = M H
+    PK = Mmat @ s.H().toarray()
+    A = s.A().toarray(); Bt = s.B.T.toarray(); Hp = s.H_p().toarray()
+    Xi = commutator(s).toarray()
+    Hp_inv_Xi = np.linalg.solve(Hp, Xi)
+    nu = s.nu_total
+    top_left = np.eye(nu) - np.linalg.solve(A, Bt @ Hp_inv_Xi)
+    np.testing.assert_allclose(PK[:nu, :nu], top_left, atol=1e-10)
+    np.testing.assert_allclose(PK[:nu, nu:], 0.0, atol=1e-10)
+    np.testing.assert_allclose(PK[nu:, :nu], Hp_inv_Xi, atol=1e-10)
+    np.testing.assert_allclose(PK[nu:, nu:], np.eye(s.ncell), atol=1e-10)
+
+
+@pytest.mark.parametrize("n", [(32, 24), (8, 8, 6)])
+def test_constant_medium_exact_blocks_one_iteration(n):
+    """Constant rho, mu, lambda, gamma: Xi = 0, so P = K and the
+    preconditioned system is the identity -- FGMRES converges in one
+    iteration (with a lucky Arnoldi breakdown)."""
+    vp, vs, rho = W.constant_medium(n, 2.0, 1.0, 1.0)
+    s = ElasticSystem(n, (1.0,) * len(n), vp, vs, rho, omega=0.6, abc_width=0)
+    M = BlockAcoustic(s, alpha=0.0, solver="exact")
+    b = np.zeros(s.ndof, dtype=np.complex128)
+    b[s.face_sizes[0] + s.face_sizes[1] // 2] = -1.0
+    H = s.H()
+    res = fgmres(lambda x: H @ x, M, b, restart=20, tol=1e-10, maxit=50)
+    assert res.iters == 1
+    assert res.relres_true < 1e-10
+
+
+def _linear_problem(n1, n2, omega, lam_factor):
+    n = (n1, n2)
+    h = (16.0 / n1, 5.0 / n2)
+    vp, vs, rho = W.linear_medium(n, lam_factor=lam_factor)
+    s = ElasticSystem(n, h, vp, vs, rho, omega=omega, abc_width=20,
+                      abc_sides=W.abc_all_but_top(2))
+    b = W.point_source_rhs(n, h, [(1, (n1 // 2, 1))])[0]
+    return s, b
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("row", [0, 1])
+def test_table_scalability_linear(row):
+    """Non-restarted GMRES with exactly solved blocks on the paper's linear
+    media reproduces Table scalability_linear within one iteration."""
+    g = json.load(open(os.path.join(GOLD, "tab_scalability_linear.json")))
+    r = g["rows"][row]
+    for lf, expect in zip(g["columns"], r["iters"]):
+        s, b = _linear_problem(*r["grid"], r["omega_over_pi"] * math.pi, lf)
+        M = BlockAcoustic(s, alpha=0.0, solver="exact")
+        H = s.H()
+        res = fgmres(lambda x: H @ x, M, b, restart=1000, tol=1e-6, maxit=200)
+        assert res.relres_true < 1e-6
+        assert abs(res.iters - expect) <= 1, (r["grid"], lf, res.iters, expect)
+
+
+@pytest.mark.slow
+def test_table_2Dlinear_block_acoustic_wcycle():
+    """GMRES(5) with one W(1,2) damped-Jacobi cycle per block on the linear
+    media at 400 x 128, 2/3/4 levels, reproduces the block-acoustic columns
+    of Table 2Dlinear within 10%."""
+    g = json.load(open(os.path.join(GOLD, "tab_2Dlinear.json")))
+    r = g["rows"][0]
+    s, b = _linear_problem(*r["grid"], r["omega_over_pi"] * math.pi, 1.0)
+    H = s.H()
+    for L, a, expect in zip(r["levels"], r["alpha"], r["iters"]):
+        M = BlockAcoustic(s, alpha=a, solver="mg", levels=L, cycle="W",
+                          nu=(1, 2), damping=(0.8, 0.8, 0.3))
+        res = fgmres(lambda x: H @ x, M, b, restart=5, tol=1e-6, maxit=500)
+        assert res.relres_true < 1e-6
+        assert abs(res.iters - expect) <= 0.1 * expect, (L, res.iters, expect)
