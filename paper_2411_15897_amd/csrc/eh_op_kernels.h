@@ -1,0 +1,154 @@
+// Elastic operator, distributor and coupling kernels (FP64 inputs).
+//
+//  k_op_face / k_op_cell: y = H x (eq. mixed-discretized).  Rows of u_k:
+//      A_k u_k + B_k^T p with B_k^T p = (p(c) - p(c - e_k)) / h_k at the
+//      k-face between cells c - e_k and c (zero ghost p outside).
+//      Rows of p: B u - C p = -sum_k (u_k(hi face) - u_k(lo face)) / h_k
+//      - p / (lambda + mu).
+//  k_distribute: t = B r_u - A_p r_p (eq. mixed-distributed) with
+//      A_p r = B B^T (mu r) - w^2 rho (1 - i gamma/w) r (eq. Ap), written in
+//      the multigrid precision.
+//  k_couple: g_k = r_k - B_k^T e_p (the second block row of eq. prec).
+//
+// Same launch shape as the multigrid kernels.
+#pragma once
+
+#include "eh_common.h"
+#include "eh_mg_kernels.h"
+
+namespace eh {
+
+// Face (i,j,k) of the k-face grid touches cells with index i_a - 1 and i_a
+// along a = kaxis.  Returns the linear cell index of the cell at offset
+// `off` (0 or -1) along kaxis, or -1 when it lies outside.
+__device__ __forceinline__ int64_t face_cell(const Dims& dc, int kaxis, int i, int j, int k, int off) {
+    int c[3] = {i, j, k};
+    c[kaxis] += off;
+    if (c[kaxis] < 0 || c[kaxis] >= dc.g[kaxis]) return -1;
+    return ((int64_t)c[2] * dc.g[1] + c[1]) * dc.g[0] + c[0];
+}
+
+template <class Tin, int DIM>
+__global__ void __launch_bounds__(256)
+k_op_face(Dims d, Dims dc, int kaxis, const double* __restrict__ w0, const double* __restrict__ w1,
+          const double* __restrict__ w2, const c128* __restrict__ D0, const cplx<Tin>* __restrict__ u,
+          const cplx<Tin>* __restrict__ pf, double ihk, c128* __restrict__ y, int nrhs,
+          int64_t vs_in, int64_t vs_out) {
+    EH_POINT_INDEX(d)
+    FineCoef<double, 0, DIM> c;
+    c.load(d, i, j, k, p, w0, w1, w2, 0.0, 0.0, 0.0);
+    const c128 Dp = D0[p];
+    const int64_t chi = face_cell(dc, kaxis, i, j, k, 0);
+    const int64_t clo = face_cell(dc, kaxis, i, j, k, -1);
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx<Tin>* ur = u + r * vs_in;
+        const cplx<Tin>* pr = pf + r * vs_in;
+        // off-diagonal sum in FP64
+        c128 s = mk(0.0, 0.0);
+        if (i + 1 < d.g[0]) s = s + c.cp[0] * ccast<double>(ur[p + 1]);
+        if (i > 0) s = s + c.cm[0] * ccast<double>(ur[p - 1]);
+        if (j + 1 < d.g[1]) s = s + c.cp[1] * ccast<double>(ur[p + sy]);
+        if (j > 0) s = s + c.cm[1] * ccast<double>(ur[p - sy]);
+        if (DIM == 3) {
+            if (k + 1 < d.g[2]) s = s + c.cp[2] * ccast<double>(ur[p + sz]);
+            if (k > 0) s = s + c.cm[2] * ccast<double>(ur[p - sz]);
+        }
+        c128 g = mk(0.0, 0.0);
+        if (chi >= 0) g = g + ccast<double>(pr[chi]);
+        if (clo >= 0) g = g - ccast<double>(pr[clo]);
+        y[r * vs_out + p] = Dp * ccast<double>(ur[p]) - s + ihk * g;
+    }
+}
+
+template <class Tin, int DIM>
+__global__ void __launch_bounds__(256)
+k_op_cell(Dims dc, const cplx<Tin>* __restrict__ u0, const cplx<Tin>* __restrict__ u1,
+          const cplx<Tin>* __restrict__ u2, const cplx<Tin>* __restrict__ pf,
+          const double* __restrict__ C, double ih0, double ih1, double ih2, c128* __restrict__ y,
+          int nrhs, int64_t vs_in, int64_t vs_out) {
+    EH_POINT_INDEX(dc)
+    // face-grid strides: u0 grid (g0+1, g1, g2), u1 (g0, g1+1, g2), u2 (g0, g1, g2+1)
+    const int64_t f0 = ((int64_t)k * dc.g[1] + j) * (dc.g[0] + 1) + i;
+    const int64_t f1 = ((int64_t)k * (dc.g[1] + 1) + j) * dc.g[0] + i;
+    const int64_t f2 = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
+    const int64_t s2 = (int64_t)dc.g[0] * dc.g[1];
+    const double Cp = C[p];
+    for (int r = 0; r < nrhs; ++r) {
+        const int64_t o = r * vs_in;
+        c128 div = ih0 * (ccast<double>(u0[o + f0 + 1]) - ccast<double>(u0[o + f0]));
+        div = div + ih1 * (ccast<double>(u1[o + f1 + dc.g[0]]) - ccast<double>(u1[o + f1]));
+        if (DIM == 3) div = div + ih2 * (ccast<double>(u2[o + f2 + s2]) - ccast<double>(u2[o + f2]));
+        const c128 pv = ccast<double>(pf[o + p]);
+        y[r * vs_out + p] = mk(-div.re - Cp * pv.re, -div.im - Cp * pv.im);
+    }
+}
+
+template <class T, int DIM>
+__global__ void __launch_bounds__(256)
+k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
+             const c128* __restrict__ r2, const c128* __restrict__ rp,
+             const double* __restrict__ mu, const c128* __restrict__ mcell, double om2,
+             double ih0, double ih1, double ih2, cplx<T>* __restrict__ t, int nrhs,
+             int64_t vs_in, int64_t vs_out) {
+    EH_POINT_INDEX(dc)
+    const int64_t f0 = ((int64_t)k * dc.g[1] + j) * (dc.g[0] + 1) + i;
+    const int64_t f1 = ((int64_t)k * (dc.g[1] + 1) + j) * dc.g[0] + i;
+    const int64_t f2 = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
+    const int64_t s2 = (int64_t)dc.g[0] * dc.g[1];
+    const double ihs[3] = {ih0 * ih0, ih1 * ih1, ih2 * ih2};
+    const int64_t st[3] = {1, sy, sz};
+    const int ci[3] = {i, j, k};
+    const double mup = mu[p];
+    double mnb[3][2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        mnb[a][0] = (ci[a] > 0) ? mu[p - st[a]] : 0.0;
+        mnb[a][1] = (ci[a] + 1 < dc.g[a]) ? mu[p + st[a]] : 0.0;
+    }
+    const c128 mc = mcell[p];
+    for (int r = 0; r < nrhs; ++r) {
+        const int64_t o = r * vs_in;
+        c128 div = ih0 * (r0[o + f0 + 1] - r0[o + f0]);
+        div = div + ih1 * (r1[o + f1 + dc.g[0]] - r1[o + f1]);
+        if (DIM == 3) div = div + ih2 * (r2[o + f2 + s2] - r2[o + f2]);
+        const c128* pr = rp + o;
+        const c128 pc = pr[p];
+        // B B^T (mu r): sum_a (2 mu_c r_c - mu_c+ r_c+ - mu_c- r_c-) / h_a^2
+        c128 lap = mk(0.0, 0.0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            c128 s = (2.0 * mup) * pc;
+            if (ci[a] > 0) s = s - mnb[a][0] * pr[p - st[a]];
+            if (ci[a] + 1 < dc.g[a]) s = s - mnb[a][1] * pr[p + st[a]];
+            lap = lap + ihs[a] * s;
+        }
+        const c128 Apr = lap - om2 * (mc * pc);
+        const c128 tv = mk(-div.re - Apr.re, -div.im - Apr.im);
+        t[r * vs_out + p] = ccast<T>(tv);
+    }
+}
+
+template <class T, int DIM>
+__global__ void __launch_bounds__(256)
+k_couple(Dims d, Dims dc, int kaxis, const c128* __restrict__ ru, const cplx<T>* __restrict__ ep,
+         double ihk, cplx<T>* __restrict__ g, int nrhs, int64_t vs_r, int64_t vs_e, int64_t vs_g) {
+    EH_POINT_INDEX(d)
+    const int64_t chi = face_cell(dc, kaxis, i, j, k, 0);
+    const int64_t clo = face_cell(dc, kaxis, i, j, k, -1);
+    for (int r = 0; r < nrhs; ++r) {
+        c128 gr = mk(0.0, 0.0);
+        if (chi >= 0) gr = gr + ccast<double>(ep[r * vs_e + chi]);
+        if (clo >= 0) gr = gr - ccast<double>(ep[r * vs_e + clo]);
+        g[r * vs_g + p] = ccast<T>(ru[r * vs_r + p] - ihk * gr);
+    }
+}
+
+template <class To, class Ti>
+__global__ void __launch_bounds__(256)
+k_cast(int64_t n, const cplx<Ti>* __restrict__ in, cplx<To>* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = t; q < n; q += stride) out[q] = ccast<To>(in[q]);
+}
+
+}  // namespace eh

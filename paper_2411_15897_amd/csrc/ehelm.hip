@@ -1,0 +1,1177 @@
+// Host driver of the C-ABI library: setup of the operator and of the
+// multigrid hierarchies, the multigrid cycle schedule, the block-acoustic
+// preconditioner and the flexible GMRES iteration.  Every arithmetic step
+// of the solve runs in the kernels included below; the host only sequences
+// launches and runs the (m+1) x m Hessenberg least-squares update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ehelm.h"
+#include "eh_common.h"
+#include "eh_krylov_kernels.h"
+#include "eh_mg_kernels.h"
+#include "eh_op_kernels.h"
+#include "eh_setup_kernels.h"
+#include "eh_grad_kernels.h"
+
+using namespace eh;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HipError {
+    hipError_t e;
+    const char* where;
+};
+
+#define HIPCHK(x)                                                   \
+    do {                                                            \
+        hipError_t _e = (x);                                        \
+        if (_e != hipSuccess) throw HipError{_e, #x};               \
+    } while (0)
+
+struct ArgError {
+    std::string msg;
+};
+
+// One block of the preconditioner on one multigrid level.
+struct Level {
+    Dims d{};
+    Widths w{};              // stencil half widths (levels >= 1)
+    void* coef = nullptr;    // levels >= 1: [nst][np] complex, multigrid precision
+    void* f = nullptr;       // right-hand side          (nrhs_cap * np)
+    void* u = nullptr;       // iterate                  (nrhs_cap * np)
+    void* t = nullptr;       // Jacobi ping-pong buffer  (nrhs_cap * np)
+    void* r = nullptr;       // residual                 (nrhs_cap * np)
+    void* e = nullptr;       // cycle result             (nrhs_cap * np)
+    double damp = 0.8;
+};
+
+struct Block {
+    int kind = 0;            // 0..dim-1: A_{kind+1}; dim: H_p
+    int nodal_mask = 0;      // bit a: unknowns nodal along axis a
+    std::vector<Level> lev;
+    void* fw[3] = {nullptr, nullptr, nullptr};   // fine couplings (multigrid precision)
+    void* fD = nullptr;                          // fine diagonal (multigrid precision)
+    int64_t Nc = 0;
+    c128* Ainv = nullptr;                        // coarsest inverse, FP64, row-major
+};
+
+dim3 grid_of(const Dims& d) {
+    return dim3((unsigned)((d.g[0] + 63) / 64), (unsigned)((d.g[1] + 3) / 4), (unsigned)d.g[2]);
+}
+const dim3 kBlock(64, 4, 1);
+
+unsigned lin_grid(int64_t n, int threads = 256, int64_t cap = 65535) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    return (unsigned)std::min<int64_t>(g, cap);
+}
+
+}  // namespace
+
+struct eh_ctx {
+    int dim = 2;
+    int64_t n[3] = {1, 1, 1};
+    double h[3] = {1, 1, 1};
+    double omega = 1.0;
+    eh_opts o{};
+    hipStream_t s = nullptr;
+    int device = 0;
+    Dims dcell{};
+    Dims dface[3]{};
+    int64_t ncell = 0, ndof = 0, off[4] = {0, 0, 0, 0}, fsize[4] = {0, 0, 0, 0};
+    // FP64 coefficients of H, the distributor and the gradient
+    double* k1w[3][3] = {};
+    c128* k1D[3] = {};
+    double* C = nullptr;          // 1/(lambda+mu)
+    double* mu = nullptr;         // mu at cells
+    c128* mcell = nullptr;        // rho (1 - i gamma/w) at cells
+    double* d_vp = nullptr;
+    double* d_vs = nullptr;
+    double* d_rho = nullptr;
+    double* d_gamma = nullptr;
+    double* d_lm = nullptr;       // lambda + mu
+    double* d_edgecnt = nullptr;  // unused placeholder
+    Block blk[4];
+    int nblocks = 3;
+    int nrhs_cap = 0;
+    // Krylov workspace
+    int kry_nrhs = 0, kry_m = 0;
+    c128* V = nullptr;            // (m+1) * nrhs * ndof
+    void* Z = nullptr;            // m * nrhs * ndof, multigrid precision
+    c128* W = nullptr;            // nrhs * ndof
+    c128* partial = nullptr;
+    c128* dsmall = nullptr;       // small device arrays (coefs, results)
+    double* dscale = nullptr;
+    int kry_nblk = 0;
+    void* tmpT = nullptr;         // nrhs * ndof multigrid precision (preconditioner I/O)
+    int64_t tmpT_elems = 0;
+    std::vector<void*> allocs;
+    std::string err;
+    bool broken = false;
+
+    template <class P>
+    P* alloc(size_t count) {
+        void* p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(P));
+        if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+        allocs.push_back(p);
+        return (P*)p;
+    }
+    void release(void* p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) allocs.erase(it);
+        (void)hipFree(p);
+    }
+    size_t csize() const { return o.mg_precision == 32 ? sizeof(c64) : sizeof(c128); }
+    size_t rsize() const { return o.mg_precision == 32 ? sizeof(float) : sizeof(double); }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// setup on the host (FP64)
+
+struct HostMedium {
+    std::vector<double> mu, lm, rho, gamma;
+    std::vector<std::complex<double>> m;   // rho (1 - i gamma/w), unshifted
+};
+
+int64_t cidx(const eh_ctx* c, int i, int j, int k) {
+    return ((int64_t)k * c->n[1] + j) * c->n[0] + i;
+}
+
+// gamma = gamma0 + w * sum_a l_a^2, l_a = max(0, W - d_a)/W, d_a the distance
+// (cells, centre to side) to the nearest absorbing side along axis a
+// (Section 4: a layer of gradually increasing attenuation).
+double abc_gamma(const eh_ctx* c, int i, int j, int k) {
+    const int idx[3] = {i, j, k};
+    double g = c->o.gamma0;
+    const int W = c->o.abc_width;
+    if (W <= 0) return g;
+    for (int a = 0; a < c->dim; ++a) {
+        double d = 1e300;
+        if (c->o.abc_sides & (1u << (2 * a))) d = std::min(d, idx[a] + 0.5);
+        if (c->o.abc_sides & (1u << (2 * a + 1))) d = std::min(d, c->n[a] - idx[a] - 0.5);
+        const double l = std::max(0.0, W - d) / W;
+        g += c->omega * l * l;
+    }
+    return g;
+}
+
+// Mean of mu over the existing cells around the location whose nodal axes
+// are `nodal` (bit mask) at location index (li, lj, lk).
+double mu_mean(const eh_ctx* c, const HostMedium& M, int nodal, int li, int lj, int lk) {
+    const int L[3] = {li, lj, lk};
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (a < c->dim && (nodal & (1 << a))) { lo[a] = L[a] - 1; hi[a] = L[a]; }
+        else { lo[a] = L[a]; hi[a] = L[a]; }
+    }
+    double s = 0.0;
+    int cnt = 0;
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+                if (x < 0 || y < 0 || z < 0 || x >= c->n[0] || y >= c->n[1] || z >= c->n[2]) continue;
+                s += M.mu[cidx(c, x, y, z)];
+                ++cnt;
+            }
+    return s / cnt;
+}
+
+// Fine-level acoustic block A_k on the k-faces: couplings w_a (between a
+// face and its +e_a neighbour) and the diagonal, from grad_h^T A_e(mu) grad_h
+// - w^2 A_f(m) (eq. mixed-discretized); alpha shifts the mass (eq. shift).
+void build_Ak(const eh_ctx* c, const HostMedium& M, int kb, double alpha,
+              std::vector<double> w[3], std::vector<std::complex<double>>& D) {
+    const Dims& d = c->dface[kb];
+    const int64_t np = d.np();
+    for (int a = 0; a < c->dim; ++a) w[a].assign(np, 0.0);
+    D.assign(np, 0.0);
+    const double om2 = c->omega * c->omega;
+    for (int z = 0; z < d.g[2]; ++z)
+        for (int y = 0; y < d.g[1]; ++y)
+            for (int x = 0; x < d.g[0]; ++x) {
+                const int64_t p = ((int64_t)z * d.g[1] + y) * d.g[0] + x;
+                const int P[3] = {x, y, z};
+                double stiff = 0.0;
+                for (int a = 0; a < c->dim; ++a) {
+                    const double ih2 = 1.0 / (c->h[a] * c->h[a]);
+                    if (a == kb) {
+                        // derivative along the nodal axis lands on cells P[a]-1 and P[a]
+                        int q[3] = {x, y, z};
+                        if (P[a] < c->n[a]) {
+                            const double m = M.mu[cidx(c, q[0], q[1], q[2])] * ih2;
+                            w[a][p] = m;
+                            stiff += m;
+                        }
+                        if (P[a] >= 1) {
+                            q[a] = P[a] - 1;
+                            stiff += M.mu[cidx(c, q[0], q[1], q[2])] * ih2;
+                        }
+                    } else {
+                        // derivative along a cell-centred axis lands on edges at
+                        // node indices P[a] and P[a]+1 (zero ghost outside)
+                        const int nm = (1 << kb) | (1 << a);
+                        int q[3] = {x, y, z};
+                        const double m0 = mu_mean(c, M, nm, q[0], q[1], q[2]) * ih2;
+                        q[a] = P[a] + 1;
+                        const double m1 = mu_mean(c, M, nm, q[0], q[1], q[2]) * ih2;
+                        stiff += m0 + m1;
+                        if (P[a] + 1 < d.g[a]) w[a][p] = m1;
+                    }
+                }
+                // face mass: mean of the existing cells on both sides along kb
+                std::complex<double> mf = 0.0;
+                int cnt = 0;
+                for (int off = -1; off <= 0; ++off) {
+                    int q[3] = {x, y, z};
+                    q[kb] += off;
+                    if (q[kb] < 0 || q[kb] >= c->n[kb]) continue;
+                    const int64_t ci = cidx(c, q[0], q[1], q[2]);
+                    mf += M.rho[ci] * std::complex<double>(1.0, -(M.gamma[ci] / c->omega + alpha));
+                    ++cnt;
+                }
+                mf /= double(cnt);
+                D[p] = stiff - om2 * mf;
+            }
+}
+
+// Fine-level H_p on the cells: H_p = B B^T diag(w) - w^2 diag(m/(lambda+mu)),
+// w = (lambda + 2 mu)/(lambda + mu) (eqs. Ap, Hp); alpha shifts m.
+void build_Hp(const eh_ctx* c, const HostMedium& M, double alpha, std::vector<double>& w,
+              std::vector<std::complex<double>>& D) {
+    const int64_t nc = c->ncell;
+    w.assign(nc, 0.0);
+    D.assign(nc, 0.0);
+    double sum_ih2 = 0.0;
+    for (int a = 0; a < c->dim; ++a) sum_ih2 += 2.0 / (c->h[a] * c->h[a]);
+    const double om2 = c->omega * c->omega;
+    for (int64_t q = 0; q < nc; ++q) {
+        w[q] = 1.0 + M.mu[q] / M.lm[q];
+        const std::complex<double> ms = M.rho[q] * std::complex<double>(1.0, -(M.gamma[q] / c->omega + alpha));
+        D[q] = w[q] * sum_ih2 - om2 * ms / M.lm[q];
+    }
+}
+
+template <class T>
+void upload_real(eh_ctx* c, void** dst, const std::vector<double>& v) {
+    std::vector<T> t(v.begin(), v.end());
+    T* p = c->alloc<T>(t.size());
+    HIPCHK(hipMemcpy(p, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
+    *dst = p;
+}
+
+template <class T>
+void upload_cplx(eh_ctx* c, void** dst, const std::vector<std::complex<double>>& v) {
+    std::vector<cplx<T>> t(v.size());
+    for (size_t q = 0; q < v.size(); ++q) t[q] = mk<T>(T(v[q].real()), T(v[q].imag()));
+    cplx<T>* p = c->alloc<cplx<T>>(t.size());
+    HIPCHK(hipMemcpy(p, t.data(), t.size() * sizeof(cplx<T>), hipMemcpyHostToDevice));
+    *dst = p;
+}
+
+// FP64 stencil (half widths 1) of a fine block for the Galerkin setup.
+std::vector<c128> fine_stencil(const eh_ctx* c, const Block& B, const std::vector<double> w[3],
+                               const std::vector<std::complex<double>>& D) {
+    const Dims& d = B.lev[0].d;
+    const int64_t np = d.np();
+    Widths wd{{1, 1, c->dim == 3 ? 1 : 0}};
+    const int nst = wd.nst();
+    std::vector<c128> st((size_t)nst * np, mk(0.0, 0.0));
+    const int NX = 3, NY = 3;
+    auto put = [&](int ox, int oy, int oz, int64_t p, double v) {
+        const int o = ((oz + wd.w[2]) * NY + (oy + 1)) * NX + (ox + 1);
+        st[(size_t)o * np + p] = mk(v, 0.0);
+    };
+    const int64_t stride[3] = {1, d.g[0], (int64_t)d.g[0] * d.g[1]};
+    for (int z = 0; z < d.g[2]; ++z)
+        for (int y = 0; y < d.g[1]; ++y)
+            for (int x = 0; x < d.g[0]; ++x) {
+                const int64_t p = ((int64_t)z * d.g[1] + y) * d.g[0] + x;
+                const int P[3] = {x, y, z};
+                const int o = ((0 + wd.w[2]) * NY + 1) * NX + 1;
+                st[(size_t)o * np + p] = mk(D[p].real(), D[p].imag());
+                for (int a = 0; a < c->dim; ++a) {
+                    int e[3] = {0, 0, 0};
+                    e[a] = 1;
+                    const double ih2 = 1.0 / (c->h[a] * c->h[a]);
+                    if (P[a] + 1 < d.g[a]) {
+                        const double v = (B.kind < c->dim) ? w[a][p] : w[0][p + stride[a]] * ih2;
+                        put(e[0], e[1], e[2], p, -v);
+                    }
+                    if (P[a] >= 1) {
+                        const double v = (B.kind < c->dim) ? w[a][p - stride[a]] : w[0][p - stride[a]] * ih2;
+                        put(-e[0], -e[1], -e[2], p, -v);
+                    }
+                }
+            }
+    return st;
+}
+
+// Galerkin hierarchy (FP64 on the device) and coarsest inverse.
+void build_hierarchy(eh_ctx* c, Block& B, const std::vector<c128>& st0) {
+    const int L = (int)B.lev.size();
+    const bool f32 = c->o.mg_precision == 32;
+    c128* prev = c->alloc<c128>(st0.size());
+    HIPCHK(hipMemcpy(prev, st0.data(), st0.size() * sizeof(c128), hipMemcpyHostToDevice));
+    Widths wprev{{1, 1, c->dim == 3 ? 1 : 0}};
+    int* overflow = c->alloc<int>(1);
+    HIPCHK(hipMemset(overflow, 0, sizeof(int)));
+    for (int l = 1; l < L; ++l) {
+        Level& Lc = B.lev[l];
+        const Level& Lf = B.lev[l - 1];
+        Widths wc{{0, 0, 0}};
+        for (int a = 0; a < c->dim; ++a) wc.w[a] = (B.nodal_mask & (1 << a)) ? 1 : 2;
+        Lc.w = wc;
+        const int64_t npc = Lc.d.np();
+        c128* cur = c->alloc<c128>((size_t)wc.nst() * npc);
+        hipLaunchKernelGGL(k_galerkin, dim3(lin_grid(npc, 64, 1 << 30)), dim3(64), 0, 0, Lf.d, wprev,
+                           prev, Lc.d, wc, B.nodal_mask, cur, overflow);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipDeviceSynchronize());
+        // store in the multigrid precision
+        if (f32) {
+            c64* cf = c->alloc<c64>((size_t)wc.nst() * npc);
+            hipLaunchKernelGGL((k_cast<float, double>), dim3(lin_grid((int64_t)wc.nst() * npc)), dim3(256), 0, 0,
+                               (int64_t)wc.nst() * npc, cur, cf);
+            HIPCHK(hipGetLastError());
+            Lc.coef = cf;
+        } else {
+            c128* cf = c->alloc<c128>((size_t)wc.nst() * npc);
+            HIPCHK(hipMemcpy(cf, cur, (size_t)wc.nst() * npc * sizeof(c128), hipMemcpyDeviceToDevice));
+            Lc.coef = cf;
+        }
+        HIPCHK(hipDeviceSynchronize());
+        c->release(prev);
+        prev = cur;
+        wprev = wc;
+    }
+    int ov = 0;
+    HIPCHK(hipMemcpy(&ov, overflow, sizeof(int), hipMemcpyDeviceToHost));
+    c->release(overflow);
+    if (ov) throw ArgError{"internal: Galerkin stencil exceeded its width"};
+    // coarsest: dense inverse by Gauss-Jordan with partial pivoting (FP64)
+    const Level& Lc = B.lev[L - 1];
+    const int64_t N = Lc.d.np();
+    if (N > 20000) throw ArgError{"coarsest grid too large for the dense direct solve (use more levels)"};
+    c128* M = c->alloc<c128>((size_t)N * 2 * N);
+    hipLaunchKernelGGL(k_dense_from_stencil, dim3(lin_grid(N, 64, 1 << 30)), dim3(64), 0, 0, Lc.d, wprev, prev, M);
+    HIPCHK(hipGetLastError());
+    int64_t* piv = c->alloc<int64_t>(1);
+    c128* pval = c->alloc<c128>(1);
+    c128* mult = c->alloc<c128>(N);
+    const unsigned gcols = lin_grid(2 * N);
+    for (int64_t kk = 0; kk < N; ++kk) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, 0, N, kk, M, piv, pval);
+        hipLaunchKernelGGL(k_gj_swap_scale, dim3(gcols), dim3(256), 0, 0, N, kk, M, piv, pval);
+        hipLaunchKernelGGL(k_gj_column, dim3(lin_grid(N)), dim3(256), 0, 0, N, kk, M, mult);
+        hipLaunchKernelGGL(k_gj_eliminate, dim3(gcols, (unsigned)N), dim3(256), 0, 0, N, kk, M, mult);
+    }
+    HIPCHK(hipGetLastError());
+    B.Nc = N;
+    B.Ainv = c->alloc<c128>((size_t)N * N);
+    hipLaunchKernelGGL(k_gj_extract, dim3(lin_grid(N * N, 256, 1 << 30)), dim3(256), 0, 0, N, M, B.Ainv);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    c->release(M);
+    c->release(piv);
+    c->release(pval);
+    c->release(mult);
+    c->release(prev);
+}
+
+void ensure_mg_workspace(eh_ctx* c, int nrhs) {
+    if (nrhs <= c->nrhs_cap) return;
+    HIPCHK(hipStreamSynchronize(c->s));
+    const size_t cs = c->csize();
+    for (int b = 0; b < c->nblocks; ++b)
+        for (auto& L : c->blk[b].lev) {
+            for (void** pp : {&L.f, &L.u, &L.t, &L.r, &L.e}) {
+                c->release(*pp);
+                *pp = c->alloc<char>((size_t)L.d.np() * nrhs * cs);
+            }
+        }
+    c->nrhs_cap = nrhs;
+}
+
+void ensure_tmpT(eh_ctx* c, int64_t elems) {
+    if (elems <= c->tmpT_elems) return;
+    HIPCHK(hipStreamSynchronize(c->s));
+    c->release(c->tmpT);
+    c->tmpT = c->alloc<char>((size_t)elems * c->csize());
+    c->tmpT_elems = elems;
+}
+
+// ---------------------------------------------------------------------------
+// multigrid cycle (Algorithm TwoCycle, recursive; V: one call, W: two)
+
+template <class T>
+void launch_op(eh_ctx* c, const Block& B, int l, int mode, const void* f, int64_t vf, const void* u,
+               int64_t vu, void* out, int64_t vo, double damp, int nrhs) {
+    const Level& L = B.lev[l];
+    const dim3 g = grid_of(L.d);
+    const T dmp = T(damp);
+    const cplx<T>* F = (const cplx<T>*)f;
+    const cplx<T>* U = (const cplx<T>*)u;
+    cplx<T>* O = (cplx<T>*)out;
+    if (l == 0) {
+        const T* w0 = (const T*)B.fw[0];
+        const T* w1 = (const T*)B.fw[1];
+        const T* w2 = (const T*)B.fw[2];
+        const T ih0 = T(1.0 / (c->h[0] * c->h[0])), ih1 = T(1.0 / (c->h[1] * c->h[1]));
+        const T ih2 = T(1.0 / (c->h[2] * c->h[2]));
+        const cplx<T>* D = (const cplx<T>*)B.fD;
+        const bool P = B.kind == c->dim;
+#define EH_FINE(KIND, DIM, MODE)                                                                   \
+    hipLaunchKernelGGL((k_fine<T, KIND, DIM, MODE>), g, kBlock, 0, c->s, L.d, w0, w1, w2, ih0, ih1, \
+                       ih2, D, F, U, O, dmp, nrhs, vf, vu, vo)
+#define EH_FINE_M(KIND, DIM)                        \
+    switch (mode) {                                 \
+        case 0: EH_FINE(KIND, DIM, 0); break;       \
+        case 1: EH_FINE(KIND, DIM, 1); break;       \
+        case 2: EH_FINE(KIND, DIM, 2); break;       \
+        default: EH_FINE(KIND, DIM, 3); break;      \
+    }
+        if (c->dim == 2) {
+            if (P) { EH_FINE_M(1, 2) } else { EH_FINE_M(0, 2) }
+        } else {
+            if (P) { EH_FINE_M(1, 3) } else { EH_FINE_M(0, 3) }
+        }
+#undef EH_FINE_M
+#undef EH_FINE
+    } else {
+        const cplx<T>* cf = (const cplx<T>*)L.coef;
+        const int wx = L.w.w[0], wy = L.w.w[1], wz = L.w.w[2];
+#define EH_ST(WX, WY, WZ, MODE)                                                                        \
+    hipLaunchKernelGGL((k_stencil<T, WX, WY, WZ, MODE>), g, kBlock, 0, c->s, L.d, cf, F, U, O, dmp, nrhs, \
+                       vf, vu, vo)
+#define EH_ST_M(WX, WY, WZ)                         \
+    switch (mode) {                                 \
+        case 0: EH_ST(WX, WY, WZ, 0); break;        \
+        case 1: EH_ST(WX, WY, WZ, 1); break;        \
+        case 2: EH_ST(WX, WY, WZ, 2); break;        \
+        default: EH_ST(WX, WY, WZ, 3); break;       \
+    }
+        if (wz == 0) {
+            if (wx == 1 && wy == 2) { EH_ST_M(1, 2, 0) }
+            else if (wx == 2 && wy == 1) { EH_ST_M(2, 1, 0) }
+            else { EH_ST_M(2, 2, 0) }
+        } else {
+            if (wx == 1) { EH_ST_M(1, 2, 2) }
+            else if (wy == 1) { EH_ST_M(2, 1, 2) }
+            else if (wz == 1) { EH_ST_M(2, 2, 1) }
+            else { EH_ST_M(2, 2, 2) }
+        }
+#undef EH_ST_M
+#undef EH_ST
+    }
+    HIPCHK(hipGetLastError());
+}
+
+template <class T>
+void dense_apply(eh_ctx* c, const Block& B, const void* f, int64_t vf, void* e, int64_t ve, int nrhs) {
+    const int N = (int)B.Nc;
+    const dim3 g((unsigned)((N + 3) / 4));
+    int r = 0;
+    while (r < nrhs) {
+        const int left = nrhs - r;
+        const cplx<T>* F = (const cplx<T>*)f + (int64_t)r * vf;
+        cplx<T>* E = (cplx<T>*)e + (int64_t)r * ve;
+        if (left >= 8) {
+            hipLaunchKernelGGL((k_dense_apply<T, 8>), g, dim3(256), 0, c->s, N, B.Ainv, F, E, vf, ve);
+            r += 8;
+        } else if (left >= 4) {
+            hipLaunchKernelGGL((k_dense_apply<T, 4>), g, dim3(256), 0, c->s, N, B.Ainv, F, E, vf, ve);
+            r += 4;
+        } else if (left >= 2) {
+            hipLaunchKernelGGL((k_dense_apply<T, 2>), g, dim3(256), 0, c->s, N, B.Ainv, F, E, vf, ve);
+            r += 2;
+        } else {
+            hipLaunchKernelGGL((k_dense_apply<T, 1>), g, dim3(256), 0, c->s, N, B.Ainv, F, E, vf, ve);
+            r += 1;
+        }
+        HIPCHK(hipGetLastError());
+    }
+}
+
+template <class T>
+void copy_strided(eh_ctx* c, const void* src, int64_t vs, void* dst, int64_t vd, int64_t np, int nrhs) {
+    for (int r = 0; r < nrhs; ++r)
+        HIPCHK(hipMemcpyAsync((cplx<T>*)dst + r * vd, (const cplx<T>*)src + r * vs, np * sizeof(cplx<T>),
+                              hipMemcpyDeviceToDevice, c->s));
+}
+
+// One cycle on level l for X_l e = f.  f has stride vf; the result is
+// written to `out` (stride vo).  With guess, `out` holds the initial guess.
+template <class T>
+void cycle(eh_ctx* c, Block& B, int l, const void* f, int64_t vf, void* out, int64_t vo, bool guess,
+           int nrhs) {
+    const int Lv = (int)B.lev.size();
+    Level& L = B.lev[l];
+    const int64_t np = L.d.np();
+    if (l == Lv - 1) {
+        dense_apply<T>(c, B, f, vf, out, vo, nrhs);
+        return;
+    }
+    const int nu1 = c->o.nu_pre, nu2 = c->o.nu_post;
+    const double w = L.damp;
+    const void* cur;
+    int64_t vcur;
+    void* bufs[2] = {L.u, L.t};
+    int nb = 0;    // next internal buffer to write
+    if (guess) {
+        cur = out; vcur = vo;
+        for (int s = 0; s < nu1; ++s) {
+            void* dst = bufs[nb]; nb ^= 1;
+            launch_op<T>(c, B, l, 1, f, vf, cur, vcur, dst, np, w, nrhs);
+            cur = dst; vcur = np;
+        }
+    } else if (nu1 > 0) {
+        void* dst = bufs[nb]; nb ^= 1;
+        launch_op<T>(c, B, l, 0, f, vf, nullptr, 0, dst, np, w, nrhs);
+        cur = dst; vcur = np;
+        for (int s = 1; s < nu1; ++s) {
+            void* d2 = bufs[nb]; nb ^= 1;
+            launch_op<T>(c, B, l, 1, f, vf, cur, vcur, d2, np, w, nrhs);
+            cur = d2; vcur = np;
+        }
+    } else {
+        HIPCHK(hipMemsetAsync(L.u, 0, (size_t)np * nrhs * sizeof(cplx<T>), c->s));
+        cur = L.u; vcur = np; nb = 1;
+    }
+    // residual, restriction, coarse solve(s), prolongation
+    launch_op<T>(c, B, l, 2, f, vf, cur, vcur, L.r, np, w, nrhs);
+    Level& C = B.lev[l + 1];
+    const int64_t npc = C.d.np();
+    hipLaunchKernelGGL((k_restrict<T>), grid_of(C.d), kBlock, 0, c->s, L.d, C.d, B.nodal_mask,
+                       (const cplx<T>*)L.r, (cplx<T>*)C.f, nrhs, np, npc);
+    HIPCHK(hipGetLastError());
+    const int ncalls = (c->o.cycle == 1) ? 2 : 1;
+    for (int t = 0; t < ncalls; ++t) cycle<T>(c, B, l + 1, C.f, npc, C.e, npc, t > 0, nrhs);
+    // cur may be `out` (guess, nu1 == 0); the update is elementwise, in place
+    hipLaunchKernelGGL((k_prolong_add<T>), grid_of(L.d), kBlock, 0, c->s, L.d, C.d, B.nodal_mask,
+                       (const cplx<T>*)C.e, (cplx<T>*)cur, nrhs, vcur, npc);
+    HIPCHK(hipGetLastError());
+    for (int s = 0; s < nu2; ++s) {
+        void* dst;
+        int64_t vd;
+        if (s == nu2 - 1 && cur != out) { dst = out; vd = vo; }
+        else {
+            dst = bufs[nb]; nb ^= 1;
+            if (dst == cur) { dst = bufs[nb]; nb ^= 1; }
+            vd = np;
+        }
+        launch_op<T>(c, B, l, 1, f, vf, cur, vcur, dst, vd, w, nrhs);
+        cur = dst; vcur = vd;
+    }
+    if (cur != out) copy_strided<T>(c, cur, vcur, out, vo, np, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// operator and preconditioner
+
+template <class Tin>
+void apply_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs) {
+    const cplx<Tin>* X = (const cplx<Tin>*)x;
+    const cplx<Tin>* pf = X + c->off[c->dim];
+    for (int k = 0; k < c->dim; ++k) {
+        const Dims& d = c->dface[k];
+        if (c->dim == 2)
+            hipLaunchKernelGGL((k_op_face<Tin, 2>), grid_of(d), kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
+                               c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
+                               y + c->off[k], nrhs, vx, vy);
+        else
+            hipLaunchKernelGGL((k_op_face<Tin, 3>), grid_of(d), kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
+                               c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
+                               y + c->off[k], nrhs, vx, vy);
+        HIPCHK(hipGetLastError());
+    }
+    const cplx<Tin>* u2 = c->dim == 3 ? X + c->off[2] : X;
+    if (c->dim == 2)
+        hipLaunchKernelGGL((k_op_cell<Tin, 2>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, X + c->off[0],
+                           X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
+                           y + c->off[c->dim], nrhs, vx, vy);
+    else
+        hipLaunchKernelGGL((k_op_cell<Tin, 3>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, X + c->off[0],
+                           X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
+                           y + c->off[c->dim], nrhs, vx, vy);
+    HIPCHK(hipGetLastError());
+}
+
+// z = P^{-1} D_L r: r complex128 (stride vr), z multigrid precision (stride vz)
+template <class T>
+void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs) {
+    ensure_mg_workspace(c, nrhs);
+    const int d = c->dim;
+    Block& Bp = c->blk[d];
+    Level& Lp = Bp.lev[0];
+    const c128* r2 = d == 3 ? r + c->off[2] : r;
+    if (d == 2)
+        hipLaunchKernelGGL((k_distribute<T, 2>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, r + c->off[0],
+                           r + c->off[1], r2, r + c->off[d], c->mu, c->mcell, c->omega * c->omega,
+                           1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell);
+    else
+        hipLaunchKernelGGL((k_distribute<T, 3>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, r + c->off[0],
+                           r + c->off[1], r2, r + c->off[d], c->mu, c->mcell, c->omega * c->omega,
+                           1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell);
+    HIPCHK(hipGetLastError());
+    cplx<T>* Z = (cplx<T>*)z;
+    cplx<T>* ep = Z + c->off[d];
+    cycle<T>(c, Bp, 0, Lp.f, c->ncell, ep, vz, false, nrhs);
+    for (int k = 0; k < d; ++k) {
+        Block& Bk = c->blk[k];
+        Level& Lk = Bk.lev[0];
+        const int64_t np = Lk.d.np();
+        if (d == 2)
+            hipLaunchKernelGGL((k_couple<T, 2>), grid_of(Lk.d), kBlock, 0, c->s, Lk.d, c->dcell, k, r + c->off[k],
+                               (const cplx<T>*)ep, 1.0 / c->h[k], (cplx<T>*)Lk.f, nrhs, vr, vz, np);
+        else
+            hipLaunchKernelGGL((k_couple<T, 3>), grid_of(Lk.d), kBlock, 0, c->s, Lk.d, c->dcell, k, r + c->off[k],
+                               (const cplx<T>*)ep, 1.0 / c->h[k], (cplx<T>*)Lk.f, nrhs, vr, vz, np);
+        HIPCHK(hipGetLastError());
+        cycle<T>(c, Bk, 0, Lk.f, np, Z + c->off[k], vz, false, nrhs);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Krylov helpers
+
+void ensure_krylov(eh_ctx* c, int nrhs, int m) {
+    if (nrhs <= c->kry_nrhs && m <= c->kry_m) return;
+    HIPCHK(hipStreamSynchronize(c->s));
+    c->release(c->V); c->release(c->Z); c->release(c->W); c->release(c->partial);
+    c->release(c->dsmall); c->release(c->dscale);
+    c->V = c->alloc<c128>((size_t)(m + 1) * nrhs * c->ndof);
+    c->Z = c->alloc<char>((size_t)m * nrhs * c->ndof * c->csize());
+    c->W = c->alloc<c128>((size_t)nrhs * c->ndof);
+    c->kry_nblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (c->ndof + 1023) / 1024));
+    c->partial = c->alloc<c128>((size_t)c->kry_nblk * nrhs * (m + 1));
+    c->dsmall = c->alloc<c128>((size_t)4 * nrhs * (m + 2));
+    c->dscale = c->alloc<double>(nrhs);
+    c->kry_nrhs = nrhs;
+    c->kry_m = m;
+}
+
+// Gram-Schmidt pass over columns [0, m): MODE as in k_gs.  coef/out are
+// device arrays [nrhs][m] (out: [nrhs][1] for norms).
+template <int MODE>
+void gs_pass(eh_ctx* c, int m, int nrhs, const c128* V, c128* w, const c128* coef, c128* out) {
+    const int nblk = c->kry_nblk;
+    hipLaunchKernelGGL((k_gs<MODE>), dim3(nblk, nrhs), dim3(KRY_THREADS), 0, c->s, c->ndof, m, nrhs, V, w,
+                       coef, c->partial);
+    HIPCHK(hipGetLastError());
+    const int mm = (MODE == 0 || MODE == 1) ? m : 1;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(lin_grid((int64_t)nrhs * mm)), dim3(256), 0, c->s, nblk, mm,
+                       nrhs, c->partial, out);
+    HIPCHK(hipGetLastError());
+}
+
+void norms(eh_ctx* c, const c128* w, int nrhs, std::vector<double>& out) {
+    c128* d = c->dsmall;
+    gs_pass<3>(c, 1, nrhs, nullptr, const_cast<c128*>(w), nullptr, d);
+    std::vector<c128> h(nrhs);
+    HIPCHK(hipMemcpyAsync(h.data(), d, nrhs * sizeof(c128), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    out.resize(nrhs);
+    for (int r = 0; r < nrhs; ++r) out[r] = std::sqrt(h[r].re);
+}
+
+void scale_into(eh_ctx* c, const c128* w, c128* v, const std::vector<double>& s, int nrhs) {
+    HIPCHK(hipMemcpyAsync(c->dscale, s.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->s));
+    hipLaunchKernelGGL(k_scale, dim3(lin_grid(c->ndof, 256, 2048), nrhs), dim3(256), 0, c->s, c->ndof, nrhs,
+                       c->dscale, w, v);
+    HIPCHK(hipGetLastError());
+}
+
+typedef std::complex<double> cd;
+
+template <class T>
+eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, int maxit, eh_info* info) {
+    const int m = c->o.restart;
+    ensure_krylov(c, nrhs, m);
+    const int64_t n = c->ndof;
+    const int64_t vstep = (int64_t)nrhs * n;    // distance between basis vectors
+    cplx<T>* Z = (cplx<T>*)c->Z;
+    std::vector<double> bnorm, beta;
+    norms(c, b, nrhs, bnorm);
+    HIPCHK(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(c128), c->s));
+    std::vector<int> done(nrhs, 0), its(nrhs, 0);
+    std::vector<double> est(nrhs, 1.0);
+    for (int r = 0; r < nrhs; ++r) if (bnorm[r] == 0.0) { done[r] = 1; est[r] = 0.0; }
+    int total = 0;
+    bool first = true;
+    std::vector<cd> Hh((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), cs((size_t)nrhs * m),
+        sn((size_t)nrhs * m);
+    std::vector<int> jr(nrhs, 0), active(nrhs, 0);
+    std::vector<c128> h1((size_t)nrhs * m), h2((size_t)nrhs * m), nr(nrhs);
+    std::vector<c128> ydev((size_t)nrhs * m);
+    while (total < maxit) {
+        // r = b - H x
+        if (first) {
+            HIPCHK(hipMemcpyAsync(c->W, b, (size_t)nrhs * n * sizeof(c128), hipMemcpyDeviceToDevice, c->s));
+        } else {
+            apply_H<double>(c, x, n, c->V, n, nrhs);      // V_0 slot as scratch
+            hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, b, c->V, c->W);
+            HIPCHK(hipGetLastError());
+        }
+        first = false;
+        norms(c, c->W, nrhs, beta);
+        bool any = false;
+        std::vector<double> sc(nrhs, 0.0);
+        for (int r = 0; r < nrhs; ++r) {
+            if (!done[r] && beta[r] / bnorm[r] < tol) { done[r] = 1; est[r] = beta[r] / bnorm[r]; }
+            if (!std::isfinite(beta[r])) { c->err = "non-finite residual"; return EH_ERR_STATE; }
+            active[r] = !done[r];
+            if (active[r]) { any = true; sc[r] = 1.0 / beta[r]; }
+            jr[r] = 0;
+            for (int q = 0; q <= m; ++q) g[(size_t)r * (m + 1) + q] = 0.0;
+            g[(size_t)r * (m + 1)] = beta[r];
+        }
+        if (!any) break;
+        scale_into(c, c->W, c->V, sc, nrhs);
+        int j = 0;
+        for (; j < m && total < maxit; ++j) {
+            c128* Vj = c->V + (int64_t)j * vstep;
+            cplx<T>* Zj = Z + (int64_t)j * vstep;
+            apply_M<T>(c, Vj, n, Zj, n, nrhs);
+            apply_H<T>(c, Zj, n, c->W, n, nrhs);
+            ++total;
+            // classical Gram-Schmidt, twice
+            c128* d1 = c->dsmall;
+            c128* d2 = c->dsmall + (size_t)nrhs * (m + 2);
+            c128* d3 = c->dsmall + (size_t)2 * nrhs * (m + 2);
+            gs_pass<0>(c, j + 1, nrhs, c->V, c->W, nullptr, d1);
+            gs_pass<1>(c, j + 1, nrhs, c->V, c->W, d1, d2);
+            gs_pass<2>(c, j + 1, nrhs, c->V, c->W, d2, d3);
+            HIPCHK(hipMemcpyAsync(h1.data(), d1, (size_t)nrhs * (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipMemcpyAsync(h2.data(), d2, (size_t)nrhs * (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipMemcpyAsync(nr.data(), d3, (size_t)nrhs * sizeof(c128), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipStreamSynchronize(c->s));
+            bool any_active = false;
+            std::vector<double> s2(nrhs, 0.0);
+            for (int r = 0; r < nrhs; ++r) {
+                if (!active[r]) continue;
+                cd* col = &Hh[((size_t)r * m + j) * (m + 1)];
+                for (int i = 0; i <= j; ++i)
+                    col[i] = cd(h1[(size_t)r * (j + 1) + i].re + h2[(size_t)r * (j + 1) + i].re,
+                                h1[(size_t)r * (j + 1) + i].im + h2[(size_t)r * (j + 1) + i].im);
+                const double hn = std::sqrt(std::max(0.0, nr[r].re));
+                double w0 = 0.0;
+                for (int i = 0; i <= j; ++i) w0 += std::norm(col[i]);
+                w0 = std::sqrt(w0 + hn * hn);
+                col[j + 1] = hn;
+                // previous rotations
+                for (int i = 0; i < j; ++i) {
+                    const cd ci = cs[(size_t)r * m + i], si = sn[(size_t)r * m + i];
+                    const cd a = col[i], bb = col[i + 1];
+                    col[i] = ci * a + si * bb;
+                    col[i + 1] = -std::conj(si) * a + ci * bb;
+                }
+                // new rotation zeroing col[j+1]
+                const cd a = col[j];
+                const double bb = std::abs(col[j + 1]);
+                const double nu = std::sqrt(std::norm(a) + bb * bb);
+                cd ci, si;
+                if (std::abs(a) == 0.0) { ci = 0.0; si = 1.0; }
+                else { ci = std::abs(a) / nu; si = (a / std::abs(a)) * bb / nu; }
+                cs[(size_t)r * m + j] = ci;
+                sn[(size_t)r * m + j] = si;
+                col[j] = ci * a + si * col[j + 1];
+                col[j + 1] = 0.0;
+                cd* gr = &g[(size_t)r * (m + 1)];
+                gr[j + 1] = -std::conj(si) * gr[j];
+                gr[j] = ci * gr[j];
+                jr[r] = j + 1;
+                its[r] += 1;
+                est[r] = std::abs(gr[j + 1]) / bnorm[r];
+                const bool brk = hn <= 1e-14 * w0;
+                if (!std::isfinite(est[r])) { c->err = "non-finite Arnoldi coefficient"; return EH_ERR_STATE; }
+                if (est[r] < tol || brk) active[r] = 0;
+                else { s2[r] = 1.0 / hn; any_active = true; }
+            }
+            if (!any_active || j == m - 1 || total >= maxit) { ++j; break; }
+            scale_into(c, c->W, c->V + (int64_t)(j + 1) * vstep, s2, nrhs);
+        }
+        // x += Z y, y from the triangular system R y = g
+        int mmax = 0;
+        std::fill(ydev.begin(), ydev.end(), mk(0.0, 0.0));
+        for (int r = 0; r < nrhs; ++r) {
+            const int jj = jr[r];
+            if (jj == 0) continue;
+            mmax = std::max(mmax, jj);
+            std::vector<cd> y(jj);
+            for (int i = jj - 1; i >= 0; --i) {
+                cd s = g[(size_t)r * (m + 1) + i];
+                for (int q = i + 1; q < jj; ++q) s -= Hh[((size_t)r * m + q) * (m + 1) + i] * y[q];
+                y[i] = s / Hh[((size_t)r * m + i) * (m + 1) + i];
+            }
+            for (int i = 0; i < jj; ++i) ydev[(size_t)r * m + i] = mk(y[i].real(), y[i].imag());
+        }
+        if (mmax > 0) {
+            c128* dy = c->dsmall + (size_t)3 * nrhs * (m + 2);
+            HIPCHK(hipMemcpyAsync(dy, ydev.data(), (size_t)nrhs * m * sizeof(c128), hipMemcpyHostToDevice, c->s));
+            hipLaunchKernelGGL((k_xupdate<T>), dim3(lin_grid(n, 256, 2048), nrhs), dim3(256), 0, c->s, n, m, nrhs,
+                               (const cplx<T>*)Z, dy, x);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    // true residual in FP64
+    apply_H<double>(c, x, n, c->V, n, nrhs);
+    hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, b, c->V, c->W);
+    HIPCHK(hipGetLastError());
+    std::vector<double> rn;
+    norms(c, c->W, nrhs, rn);
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+        const double rel = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
+        const int conv = rel < tol;
+        all = all && conv;
+        if (info) {
+            info[r].iters = its[r];
+            info[r].converged = conv;
+            info[r].relres_true = rel;
+            info[r].relres_est = est[r];
+        }
+    }
+    return all ? EH_OK : EH_NOT_CONVERGED;
+}
+
+eh_status fail(eh_ctx* c, eh_status st, const std::string& msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+eh_status from_hip(eh_ctx* c, const HipError& e) {
+    std::string m = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where;
+    if (c) { c->err = m; c->broken = true; }
+    else g_create_error = m;
+    return e.e == hipErrorOutOfMemory ? EH_ERR_OOM : EH_ERR_HIP;
+}
+
+void destroy_all(eh_ctx* c) {
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+void eh_default_opts(eh_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->levels = 3;
+    o->cycle = 0;
+    o->nu_pre = 1;
+    o->nu_post = 2;
+    o->n_damping = 3;
+    o->damping[0] = 0.8;
+    o->damping[1] = 0.8;
+    o->damping[2] = 0.3;
+    o->alpha = 0.1;
+    o->mg_precision = 32;
+    o->restart = 20;
+    o->abc_width = 20;
+    o->abc_sides = 0;   // filled per dim in eh_create when zero: all but the top
+    o->gamma0 = 0.01 * M_PI;
+}
+
+const char* eh_last_error(const eh_ctx* c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+int64_t eh_ndof(const eh_ctx* c) { return c ? c->ndof : 0; }
+
+eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, const double* vp,
+                    const double* vs, const double* rho, double omega, const eh_opts* opts, void* stream) {
+    g_create_error.clear();
+    if (!out) { g_create_error = "ctx pointer is NULL"; return EH_ERR_ARG; }
+    *out = nullptr;
+    if (dim != 2 && dim != 3) { g_create_error = "dim must be 2 or 3"; return EH_ERR_ARG; }
+    if (!n || !h || !vp || !vs || !rho) { g_create_error = "NULL array argument"; return EH_ERR_ARG; }
+    if (!(omega > 0.0) || !std::isfinite(omega)) { g_create_error = "omega must be positive"; return EH_ERR_ARG; }
+    eh_opts o;
+    if (opts) o = *opts; else eh_default_opts(&o);
+    if (o.abc_sides == 0 && !opts) {
+        o.abc_sides = (1u << (2 * dim)) - 1u;
+        o.abc_sides &= ~(1u << (2 * (dim - 1)));
+    }
+    if (o.levels < 1 || o.levels > 12) { g_create_error = "levels must be in [1, 12]"; return EH_ERR_ARG; }
+    if (o.cycle != 0 && o.cycle != 1) { g_create_error = "cycle must be 0 (V) or 1 (W)"; return EH_ERR_ARG; }
+    if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post < 1 || o.nu_pre > 16 || o.nu_post > 16) {
+        g_create_error = "invalid smoothing counts"; return EH_ERR_ARG;
+    }
+    if (o.n_damping < 1 || o.n_damping > 8) { g_create_error = "n_damping must be in [1, 8]"; return EH_ERR_ARG; }
+    if (o.mg_precision != 32 && o.mg_precision != 64) { g_create_error = "mg_precision must be 32 or 64"; return EH_ERR_ARG; }
+    if (o.restart < 1 || o.restart > KRY_MAXM) { g_create_error = "restart must be in [1, 32]"; return EH_ERR_ARG; }
+    if (o.abc_width < 0) { g_create_error = "abc_width must be >= 0"; return EH_ERR_ARG; }
+    if (!(o.alpha >= 0.0) || !std::isfinite(o.alpha)) { g_create_error = "alpha must be >= 0"; return EH_ERR_ARG; }
+    int64_t ncell = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (n[a] < 2 || n[a] > (1 << 20)) { g_create_error = "grid size out of range"; return EH_ERR_ARG; }
+        if (n[a] % (int64_t(1) << (o.levels - 1)) != 0) {
+            g_create_error = "each n must be divisible by 2^(levels-1)"; return EH_ERR_ARG;
+        }
+        if (!(h[a] > 0.0) || !std::isfinite(h[a])) { g_create_error = "h must be positive"; return EH_ERR_ARG; }
+        ncell *= n[a];
+    }
+    if (dim == 2 && n[1] > 65535 * 4) { g_create_error = "grid too tall"; return EH_ERR_ARG; }
+    for (int64_t q = 0; q < ncell; ++q) {
+        if (!(rho[q] > 0.0) || !(vs[q] > 0.0) || !(vp[q] > vs[q]) || !std::isfinite(vp[q]) ||
+            !std::isfinite(rho[q])) {
+            g_create_error = "medium must satisfy vp > vs > 0 and rho > 0 (finite) in every cell";
+            return EH_ERR_ARG;
+        }
+    }
+    eh_ctx* c = new (std::nothrow) eh_ctx();
+    if (!c) { g_create_error = "out of host memory"; return EH_ERR_OOM; }
+    try {
+        c->dim = dim;
+        for (int a = 0; a < 3; ++a) { c->n[a] = a < dim ? n[a] : 1; c->h[a] = a < dim ? h[a] : 1.0; }
+        c->omega = omega;
+        c->o = o;
+        c->s = (hipStream_t)stream;
+        HIPCHK(hipGetDevice(&c->device));
+        c->dcell = Dims{{(int)c->n[0], (int)c->n[1], (int)c->n[2]}};
+        c->ncell = ncell;
+        int64_t acc = 0;
+        for (int k = 0; k < dim; ++k) {
+            Dims d = c->dcell;
+            d.g[k] += 1;
+            c->dface[k] = d;
+            c->off[k] = acc;
+            c->fsize[k] = d.np();
+            acc += d.np();
+        }
+        c->off[dim] = acc;
+        c->fsize[dim] = ncell;
+        c->ndof = acc + ncell;
+        c->nblocks = dim + 1;
+        // medium
+        HostMedium M;
+        M.mu.resize(ncell); M.lm.resize(ncell); M.rho.resize(ncell); M.gamma.resize(ncell); M.m.resize(ncell);
+        for (int z = 0; z < c->n[2]; ++z)
+            for (int y = 0; y < c->n[1]; ++y)
+                for (int x = 0; x < c->n[0]; ++x) {
+                    const int64_t q = cidx(c, x, y, z);
+                    M.mu[q] = rho[q] * vs[q] * vs[q];
+                    M.lm[q] = rho[q] * (vp[q] * vp[q] - vs[q] * vs[q]);
+                    M.rho[q] = rho[q];
+                    M.gamma[q] = abc_gamma(c, x, y, z);
+                    M.m[q] = rho[q] * std::complex<double>(1.0, -M.gamma[q] / omega);
+                }
+        // FP64 arrays for H, the distributor and the gradient
+        {
+            std::vector<double> Cv(ncell);
+            for (int64_t q = 0; q < ncell; ++q) Cv[q] = 1.0 / M.lm[q];
+            upload_real<double>(c, (void**)&c->C, Cv);
+            upload_real<double>(c, (void**)&c->mu, M.mu);
+            upload_cplx<double>(c, (void**)&c->mcell, M.m);
+            upload_real<double>(c, (void**)&c->d_rho, M.rho);
+            upload_real<double>(c, (void**)&c->d_gamma, M.gamma);
+            upload_real<double>(c, (void**)&c->d_lm, M.lm);
+            std::vector<double> tmp(vp, vp + ncell);
+            upload_real<double>(c, (void**)&c->d_vp, tmp);
+            tmp.assign(vs, vs + ncell);
+            upload_real<double>(c, (void**)&c->d_vs, tmp);
+        }
+        const bool f32 = o.mg_precision == 32;
+        for (int b = 0; b <= dim; ++b) {
+            Block& B = c->blk[b];
+            B.kind = b;
+            B.nodal_mask = b < dim ? (1 << b) : 0;
+            B.lev.resize(o.levels);
+            for (int l = 0; l < o.levels; ++l) {
+                Dims d{};
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t na = a < dim ? (c->n[a] >> l) : 1;
+                    d.g[a] = (int)(na + ((B.nodal_mask >> a) & 1));
+                }
+                B.lev[l].d = d;
+                B.lev[l].damp = o.damping[std::min(l, o.n_damping - 1)];
+            }
+            std::vector<double> w[3];
+            std::vector<std::complex<double>> D, D0;
+            if (b < dim) {
+                build_Ak(c, M, b, o.alpha, w, D);
+                std::vector<double> w0[3];
+                build_Ak(c, M, b, 0.0, w0, D0);
+                for (int a = 0; a < dim; ++a) upload_real<double>(c, (void**)&c->k1w[b][a], w0[a]);
+                upload_cplx<double>(c, (void**)&c->k1D[b], D0);
+                for (int a = 0; a < dim; ++a) {
+                    if (f32) upload_real<float>(c, &B.fw[a], w[a]);
+                    else upload_real<double>(c, &B.fw[a], w[a]);
+                }
+            } else {
+                build_Hp(c, M, o.alpha, w[0], D);
+                if (f32) upload_real<float>(c, &B.fw[0], w[0]);
+                else upload_real<double>(c, &B.fw[0], w[0]);
+            }
+            if (f32) upload_cplx<float>(c, &B.fD, D);
+            else upload_cplx<double>(c, &B.fD, D);
+            const std::vector<c128> st0 = fine_stencil(c, B, w, D);
+            build_hierarchy(c, B, st0);
+        }
+        ensure_mg_workspace(c, 1);
+        HIPCHK(hipDeviceSynchronize());
+    } catch (const HipError& e) {
+        from_hip(nullptr, e);
+        destroy_all(c);
+        delete c;
+        return e.e == hipErrorOutOfMemory ? EH_ERR_OOM : EH_ERR_HIP;
+    } catch (const ArgError& e) {
+        g_create_error = e.msg;
+        destroy_all(c);
+        delete c;
+        return EH_ERR_ARG;
+    } catch (const std::bad_alloc&) {
+        g_create_error = "out of host memory";
+        destroy_all(c);
+        delete c;
+        return EH_ERR_OOM;
+    }
+    *out = c;
+    return EH_OK;
+}
+
+void eh_destroy(eh_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->s);
+    destroy_all(c);
+    delete c;
+}
+
+eh_status eh_set_stream(eh_ctx* c, void* stream) {
+    if (!c) return EH_ERR_ARG;
+    c->s = (hipStream_t)stream;
+    return EH_OK;
+}
+
+#define EH_GUARD(c)                                             \
+    if (!(c)) return EH_ERR_ARG;                                \
+    if ((c)->broken) return fail((c), EH_ERR_STATE, "context unusable after an earlier HIP error");
+
+eh_status eh_apply_operator(eh_ctx* c, const void* x, void* y, int nrhs) {
+    EH_GUARD(c)
+    if (!x || !y || nrhs < 1) return fail(c, EH_ERR_ARG, "invalid buffers or nrhs");
+    try {
+        apply_H<double>(c, x, c->ndof, (c128*)y, c->ndof, nrhs);
+    } catch (const HipError& e) { return from_hip(c, e); }
+    return EH_OK;
+}
+
+eh_status eh_apply_preconditioner(eh_ctx* c, const void* r, void* z, int nrhs) {
+    EH_GUARD(c)
+    if (!r || !z || nrhs < 1) return fail(c, EH_ERR_ARG, "invalid buffers or nrhs");
+    try {
+        if (c->o.mg_precision == 64) {
+            apply_M<double>(c, (const c128*)r, c->ndof, z, c->ndof, nrhs);
+        } else {
+            ensure_tmpT(c, (int64_t)nrhs * c->ndof);
+            apply_M<float>(c, (const c128*)r, c->ndof, c->tmpT, c->ndof, nrhs);
+            const int64_t tot = (int64_t)nrhs * c->ndof;
+            hipLaunchKernelGGL((k_cast<double, float>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,
+                               (const c64*)c->tmpT, (c128*)z);
+            HIPCHK(hipGetLastError());
+        }
+    } catch (const HipError& e) { return from_hip(c, e); }
+    return EH_OK;
+}
+
+eh_status eh_block_dims(const eh_ctx* c, int block, int level, int64_t* out) {
+    if (!c || !out || block < 0 || block > c->dim || level < 0 || level >= c->o.levels) return EH_ERR_ARG;
+    for (int a = 0; a < 3; ++a) out[a] = c->blk[block].lev[level].d.g[a];
+    return EH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <class T>
+void block_cycle_T(eh_ctx* c, int block, const void* f, void* e, int nrhs) {
+    ensure_mg_workspace(c, nrhs);
+    Block& B = c->blk[block];
+    Level& L = B.lev[0];
+    const int64_t np = L.d.np();
+    const int64_t tot = np * nrhs;
+    hipLaunchKernelGGL((k_cast<T, double>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,
+                       (const c128*)f, (cplx<T>*)L.f);
+    HIPCHK(hipGetLastError());
+    ensure_tmpT(c, tot);
+    cycle<T>(c, B, 0, L.f, np, c->tmpT, np, false, nrhs);
+    hipLaunchKernelGGL((k_cast<double, T>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,
+                       (const cplx<T>*)c->tmpT, (c128*)e);
+    HIPCHK(hipGetLastError());
+}
+
+template <class T>
+void block_apply_T(eh_ctx* c, int block, int level, const void* x, void* y, int nrhs) {
+    ensure_mg_workspace(c, nrhs);
+    Block& B = c->blk[block];
+    Level& L = B.lev[level];
+    const int64_t np = L.d.np();
+    const int64_t tot = np * nrhs;
+    hipLaunchKernelGGL((k_cast<T, double>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,
+                       (const c128*)x, (cplx<T>*)L.u);
+    HIPCHK(hipGetLastError());
+    launch_op<T>(c, B, level, 3, nullptr, 0, L.u, np, L.t, np, 1.0, nrhs);
+    hipLaunchKernelGGL((k_cast<double, T>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,
+                       (const cplx<T>*)L.t, (c128*)y);
+    HIPCHK(hipGetLastError());
+}
+}  // namespace
+
+extern "C" {
+
+eh_status eh_block_cycle(eh_ctx* c, int block, const void* f, void* e, int nrhs) {
+    EH_GUARD(c)
+    if (block < 0 || block > c->dim || !f || !e || nrhs < 1) return fail(c, EH_ERR_ARG, "invalid block or buffers");
+    try {
+        if (c->o.mg_precision == 64) block_cycle_T<double>(c, block, f, e, nrhs);
+        else block_cycle_T<float>(c, block, f, e, nrhs);
+    } catch (const HipError& er) { return from_hip(c, er); }
+    return EH_OK;
+}
+
+eh_status eh_block_apply(eh_ctx* c, int block, int level, const void* x, void* y, int nrhs) {
+    EH_GUARD(c)
+    if (block < 0 || block > c->dim || level < 0 || level >= c->o.levels || !x || !y || nrhs < 1)
+        return fail(c, EH_ERR_ARG, "invalid block, level or buffers");
+    try {
+        if (c->o.mg_precision == 64) block_apply_T<double>(c, block, level, x, y, nrhs);
+        else block_apply_T<float>(c, block, level, x, y, nrhs);
+    } catch (const HipError& er) { return from_hip(c, er); }
+    return EH_OK;
+}
+
+eh_status eh_solve(eh_ctx* c, const void* b, void* x, int nrhs, double tol, int maxit, eh_info* info) {
+    EH_GUARD(c)
+    if (!b || !x || nrhs < 1 || !(tol > 0.0) || maxit < 0) return fail(c, EH_ERR_ARG, "invalid solve arguments");
+    try {
+        eh_status st;
+        if (c->o.mg_precision == 64) st = solve_impl<double>(c, (const c128*)b, (c128*)x, nrhs, tol, maxit, info);
+        else st = solve_impl<float>(c, (const c128*)b, (c128*)x, nrhs, tol, maxit, info);
+        return st;
+    } catch (const HipError& e) { return from_hip(c, e); }
+}
+
+}  // extern "C"
+
+#include "eh_grad_host.inc"

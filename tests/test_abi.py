@@ -1,0 +1,94 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+declared in include/ehelm.h, fills the documented defaults, and rejects
+invalid arguments before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2411_15897_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ehelm.h")).read()
+    return sorted(set(re.findall(r"\b(eh_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.lib()
+    decl = declared_functions()
+    assert set(decl) == set(N.EXPORTED)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_default_opts():
+    L = N.lib()
+    o = N.EhOpts()
+    L.eh_default_opts(ctypes.byref(o))
+    assert (o.levels, o.cycle, o.nu_pre, o.nu_post) == (3, 0, 1, 2)
+    assert list(o.damping[:3]) == [0.8, 0.8, 0.3]
+    assert o.mg_precision == 32 and o.restart == 20 and o.abc_width == 20
+    assert o.gamma0 == pytest.approx(0.01 * math.pi)
+
+
+def _create(n, vp, vs, rho, omega=1.0, levels=2, dim=None, **kw):
+    L = N.lib()
+    dim = dim or len(n)
+    o = N.EhOpts()
+    L.eh_default_opts(ctypes.byref(o))
+    o.levels = levels
+    for k, v in kw.items():
+        setattr(o, k, v)
+    n64 = (ctypes.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
+    h = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (vp, vs, rho)]
+    ctx = ctypes.c_void_p()
+    st = L.eh_create(ctypes.byref(ctx), dim, n64, h, *(a.ctypes.data_as(dp) for a in arrs),
+                     omega, ctypes.byref(o), None)
+    return st, ctx, L.eh_last_error(None).decode()
+
+
+@pytest.mark.parametrize("case", ["vs>=vp", "rho<=0", "nan", "divisibility", "dim", "omega",
+                                  "precision", "restart", "levels"])
+def test_invalid_arguments_are_rejected_before_device_work(case):
+    n = (8, 8)
+    vp, vs, rho = np.full(64, 2.0), np.full(64, 1.0), np.full(64, 1.0)
+    kw = {}
+    omega, dim, levels = 1.0, None, 2
+    if case == "vs>=vp":
+        vs[5] = 2.5
+    elif case == "rho<=0":
+        rho[3] = 0.0
+    elif case == "nan":
+        vp[7] = float("nan")
+    elif case == "divisibility":
+        levels = 5                       # 8 is not divisible by 2^4
+    elif case == "dim":
+        dim = 4
+    elif case == "omega":
+        omega = -1.0
+    elif case == "precision":
+        kw["mg_precision"] = 16
+    elif case == "restart":
+        kw["restart"] = 0
+    elif case == "levels":
+        levels = 0
+    st, ctx, msg = _create(n, vp, vs, rho, omega=omega, levels=levels, dim=dim, **kw)
+    assert st == N.EH_ERR_ARG
+    assert ctx.value is None
+    assert len(msg) > 0
+
+
+def test_null_context_calls_are_argument_errors():
+    L = N.lib()
+    assert L.eh_apply_operator(None, None, None, 1) == N.EH_ERR_ARG
+    assert L.eh_solve(None, None, None, 1, 1e-6, 10, None) == N.EH_ERR_ARG
+    L.eh_destroy(None)
+    assert L.eh_ndof(None) == 0
