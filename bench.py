@@ -1,0 +1,187 @@
+"""Benchmark: seconds per right-hand side to a relative residual of 1e-6.
+
+One step is one full solve (FGMRES from x = 0 to ||b - Hx||/||b|| < 1e-6,
+block-acoustic preconditioner with one multigrid V-cycle per block) of the
+1024 x 1024 layered + random medium with one top point source, with all
+inputs resident in HBM.  The headline form is the complex64 multigrid under
+FP64 FGMRES; the plain FP64 form is timed beside it.  The line also carries
+the roofline figure of the dominant kernel (event-timed inside the timed
+region) and the CPU oracle's rate on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, iters_ref, n_iters):
+    """The oracle (NumPy/SciPy FP64, single thread) on the same workload:
+    setup excluded, `n_iters` FGMRES iterations timed, extrapolated to the
+    GPU's FP64 iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle.elastic import ElasticSystem
+    from oracle.fgmres import fgmres
+    from oracle.precond import BlockAcoustic
+
+    with threadpool_limits(1):
+        s = ElasticSystem(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, wl.abc_width, wl.abc_sides)
+        H = s.H()
+        M = BlockAcoustic(s, alpha=wl.alpha, solver="mg", levels=wl.levels, cycle="V",
+                          nu=wl.nu, damping=wl.damping)
+        b = W.point_source_rhs(wl.n, wl.h, wl.sources)[0]
+        t0 = time.perf_counter()
+        res = fgmres(lambda x: H @ x, M, b, restart=wl.restart, tol=wl.tol, maxit=n_iters)
+        dt = time.perf_counter() - t0
+    per_it = dt / max(res.iters, 1)
+    return {
+        "value": per_it * iters_ref,
+        "unit": "s/RHS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{res.iters} FGMRES iterations of the oracle (FP64 sparse V-cycles, "
+                   f"setup excluded) on the same 1024^2 workload, {per_it:.3f} s/iteration, "
+                   f"extrapolated to the GPU FP64 iteration count {iters_ref}"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--levels", type=int, default=None)
+    ap.add_argument("--alpha", type=float, default=None)
+    ap.add_argument("--restart", type=int, default=None)
+    ap.add_argument("--roofline-kernel", default="fine_sweep")
+    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this build "
+              "(sources would shard across GPUs with one all-reduce of the gradient at the end)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2411_15897_amd import ElasticHelmholtz
+
+    wl = W.config(args.config)
+    if args.levels: wl.levels = args.levels
+    if args.alpha is not None: wl.alpha = args.alpha
+    if args.restart: wl.restart = args.restart
+    dev = torch.device("cuda:0")
+    b = torch.from_numpy(W.point_source_rhs(wl.n, wl.h, wl.sources)).to(dev)
+    nrhs = b.shape[0]
+
+    def make(prec):
+        return ElasticHelmholtz(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, levels=wl.levels,
+                                nu=wl.nu, damping=wl.damping, alpha=wl.alpha, mg_precision=prec,
+                                restart=wl.restart, abc_width=wl.abc_width,
+                                abc_sides=wl.abc_sides)
+
+    def timed(solver, steps, warmup, kernel=None):
+        for w in range(warmup):
+            _, info = solver.solve(b, tol=wl.tol, maxit=5000)
+            log(f"warmup {w}: iters {info[0]['iters']} relres {info[0]['relres_true']:.2e}")
+        if kernel:
+            solver.timer_read(kernel)          # drop anything recorded before
+            solver.timer_enable([kernel])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for k in range(steps):
+            _, info = solver.solve(b, tol=wl.tol, maxit=5000)
+            infos.append(info)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = solver.timer_read(kernel) if kernel else None
+        solver.timer_enable([])
+        log(f"timed {steps} solves in {dt:.3f} s, iters {[i[0]['iters'] for i in infos]}")
+        return dt, infos, kt
+
+    log(f"workload {wl.name}: n={wl.n} omega={wl.omega:.4f} levels={wl.levels} alpha={wl.alpha}")
+    t_setup = time.perf_counter()
+    s32 = make(32)
+    torch.cuda.synchronize()
+    log(f"setup (complex64 multigrid) {time.perf_counter() - t_setup:.2f} s")
+    dt32, inf32, kt = timed(s32, args.steps, args.warmup, args.roofline_kernel)
+    it32 = inf32[-1][0]["iters"]
+    rel32 = max(i[0]["relres_true"] for i in inf32)
+    s32.close()
+    sec32 = dt32 / (args.steps * nrhs)
+
+    fp64 = None
+    it64 = it32
+    if not args.no_fp64:
+        s64 = make(64)
+        dt64, inf64, _ = timed(s64, max(1, min(args.steps, 2)), 1)
+        it64 = inf64[-1][0]["iters"]
+        fp64 = {"s_per_rhs": dt64 / (max(1, min(args.steps, 2)) * nrhs), "iters": it64,
+                "relres_true": max(i[0]["relres_true"] for i in inf64)}
+        s64.close()
+
+    launches, ms, nbytes = kt
+    avg_ms = ms / max(launches, 1)
+    achieved = (nbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9 if launches else None
+    roof = {
+        "kernel": args.roofline_kernel,
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+        "traffic": None,
+        "launches": launches,
+        "avg_us": avg_ms * 1e3,
+        "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
+    }
+    out = {
+        "metric": "seconds per RHS to rel. residual 1e-6; V-cycle HBM GB/s vs peak",
+        "value": sec32,
+        "unit": "s/RHS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt32 / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 multigrid / c128 FGMRES",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.n), "nrhs": nrhs, "omega": wl.omega,
+                   "levels": wl.levels, "cycle": "V(%d,%d)" % tuple(wl.nu), "alpha": wl.alpha,
+                   "restart": wl.restart, "tol": wl.tol, "iters": it32, "relres_true": rel32},
+        "fp64_plain": fp64,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl, it64, args.cpu_iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -149,6 +149,24 @@ eh_status eh_gradient(eh_ctx *ctx, const void *u, const void *w, int nrhs,
 eh_status eh_misfit(eh_ctx *ctx, const void *u, const int64_t *rec, int nrec,
                     const void *d, int nrhs, void *g, double *phi);
 
+/* Event timing of kernel classes, for measuring achieved bandwidth.
+ * Bit c of class_mask selects class c: 0 fine-level Jacobi sweep,
+ * 1 fine-level residual, 2 coarse-level (Galerkin stencil) sweeps and
+ * residuals, 3 restriction, 4 prolongation, 5 coarsest dense solve,
+ * 6 operator apply, 7 distributor, 8 coupling, 9 Krylov vector kernels,
+ * 10 fine-level first sweep from a zero guess.  While selected, every
+ * launch of the class is bracketed by two hipEvents on the context's
+ * stream.  0 disables timing. */
+eh_status eh_timer_enable(eh_ctx *ctx, unsigned class_mask);
+
+/* Sum, over the launches of class `cls` recorded since the last read, of
+ * the event-measured milliseconds and of the algorithmic bytes (each operand
+ * read once and each result written once per launch; coefficients counted
+ * once per launch, vectors once per right-hand side).  Synchronises on the
+ * recorded events and clears them. */
+eh_status eh_timer_read(eh_ctx *ctx, int cls, int64_t *launches, double *ms,
+                        double *bytes);
+
 /* Replace the stream all later work is enqueued on. */
 eh_status eh_set_stream(eh_ctx *ctx, void *hip_stream);
 

@@ -18,8 +18,14 @@ EXPORTED = [
     "eh_default_opts", "eh_create", "eh_ndof", "eh_apply_operator",
     "eh_apply_preconditioner", "eh_block_cycle", "eh_block_apply",
     "eh_block_dims", "eh_solve", "eh_gradient", "eh_misfit", "eh_set_stream",
-    "eh_destroy", "eh_last_error",
+    "eh_destroy", "eh_last_error", "eh_timer_enable", "eh_timer_read",
 ]
+
+KERNEL_CLASSES = {
+    "fine_sweep": 0, "fine_resid": 1, "coarse": 2, "restrict": 3, "prolong": 4,
+    "dense": 5, "operator": 6, "distribute": 7, "couple": 8, "krylov": 9,
+    "fine_first": 10,
+}
 
 
 class EhOpts(ctypes.Structure):
@@ -73,6 +79,10 @@ def lib():
     L.eh_gradient.restype = i32
     L.eh_misfit.argtypes = [vp, vp, vp, i32, vp, i32, vp, P(dbl)]
     L.eh_misfit.restype = i32
+    L.eh_timer_enable.argtypes = [vp, ctypes.c_uint]
+    L.eh_timer_enable.restype = i32
+    L.eh_timer_read.argtypes = [vp, i32, P(i64), P(dbl), P(dbl)]
+    L.eh_timer_read.restype = i32
     L.eh_set_stream.argtypes = [vp, vp]
     L.eh_set_stream.restype = i32
     L.eh_destroy.argtypes = [vp]

@@ -1,0 +1,375 @@
+// Multigrid kernels over a group of acoustic blocks in one launch.
+//
+// The shear blocks A_1..A_d of the preconditioner are independent (the
+// block-diagonal A of eq. prec), so each stage of their cycles -- a Jacobi
+// sweep, a residual, a restriction, a prolongation, the coarsest solve --
+// runs for all of them in a single launch: blockIdx.z enumerates
+// (slot, z-plane) pairs and every workgroup serves one block.  The pressure
+// block H_p runs as a group of one.  The per-block stencil shape is chosen
+// at compile time by a switch that is uniform across a workgroup.
+//
+// Modes of the sweep kernels:
+//   0  out = w D^-1 f                          (first sweep, zero guess)
+//   1  out = u + w D^-1 (f - X u)              (damped Jacobi)
+//   2  out = f - X u                           (residual)
+//   3  out = X u                               (operator)
+//   4  out = w D^-1 f and out2 = f - X out     (first sweep fused with the
+//      residual: the neighbours' w D^-1 f is recomputed from f and D)
+#pragma once
+
+#include "eh_common.h"
+#include "eh_mg_kernels.h"
+
+namespace eh {
+
+constexpr int GMAX = 3;
+
+template <class T>
+struct GArgs {
+    int ns;                  // slots in use
+    int kind[GMAX];          // block per slot: 0..dim-1 = A_{k+1}, dim = H_p
+    int maxg2;               // largest z extent among the slots
+    Dims d[GMAX];            // grid of the level the kernel runs on
+    Dims dc[GMAX];           // coarse grid (transfers)
+    const cplx<T>* f[GMAX];
+    const cplx<T>* u[GMAX];
+    cplx<T>* out[GMAX];
+    cplx<T>* out2[GMAX];
+    int64_t vf[GMAX], vu[GMAX], vo[GMAX], vo2[GMAX];
+    const T* w[GMAX][3];     // fine-level couplings
+    const cplx<T>* D[GMAX];  // fine-level diagonal
+    const cplx<T>* coef[GMAX];   // coarse-level stencil
+    T damp;
+    T ih[3];                 // 1 / h_a^2
+};
+
+#define EH_GROUP_POINT(a, DD)                                                   \
+    const int slot = blockIdx.z / (a).maxg2;                                    \
+    const int k = blockIdx.z - slot * (a).maxg2;                                \
+    if (slot >= (a).ns) return;                                                 \
+    const Dims d = (a).DD[slot];                                                \
+    if (k >= d.g[2]) return;                                                    \
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;                        \
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;                        \
+    if (i >= d.g[0] || j >= d.g[1]) return;                                     \
+    const int64_t sy = d.g[0], sz = (int64_t)d.g[0] * d.g[1];                   \
+    const int64_t p = k * sz + j * sy + i;
+
+// ---------------------------------------------------------------------------
+// fine level (matrix-free)
+
+template <class T, int KIND, int DIM, int MODE>
+__global__ void __launch_bounds__(256)
+k_gfine(GArgs<T> a, int nrhs) {
+    EH_GROUP_POINT(a, d)
+    const T* w0 = a.w[slot][0];
+    const T* w1 = a.w[slot][1];
+    const T* w2 = a.w[slot][2];
+    const cplx<T>* D = a.D[slot];
+    const cplx<T>* f = a.f[slot];
+    cplx<T>* out = a.out[slot];
+    const int64_t vf = a.vf[slot], vo = a.vo[slot];
+    const cplx<T> Dp = D[p];
+    const T damp = a.damp;
+    if (MODE == 0) {
+        const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
+        for (int r = 0; r < nrhs; ++r) out[r * vo + p] = sc * f[r * vf + p];
+        return;
+    }
+    FineCoef<T, KIND, DIM> c;
+    c.load(d, i, j, k, p, w0, w1, w2, a.ih[0], a.ih[1], a.ih[2]);
+    if (MODE == 4) {
+        // neighbours' first-sweep values damp * f_nb / D_nb
+        const int64_t st[3] = {1, sy, sz};
+        const int ci[3] = {i, j, k};
+        cplx<T> snb[3][2];
+        bool hasm[3], hasp[3];
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            hasm[ax] = ci[ax] > 0;
+            hasp[ax] = ci[ax] + 1 < d.g[ax];
+            snb[ax][0] = hasm[ax] ? cdiv(mk<T>(damp, T(0)), D[p - st[ax]]) : czero<T>();
+            snb[ax][1] = hasp[ax] ? cdiv(mk<T>(damp, T(0)), D[p + st[ax]]) : czero<T>();
+        }
+        const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
+        cplx<T>* out2 = a.out2[slot];
+        const int64_t vo2 = a.vo2[slot];
+        for (int r = 0; r < nrhs; ++r) {
+            const cplx<T>* fr = f + r * vf;
+            const cplx<T> fp = fr[p];
+            const cplx<T> u0 = sc * fp;
+            cplx<T> s = czero<T>();
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                if (hasm[ax]) s = s + c.cm[ax] * (snb[ax][0] * fr[p - st[ax]]);
+                if (hasp[ax]) s = s + c.cp[ax] * (snb[ax][1] * fr[p + st[ax]]);
+            }
+            out[r * vo + p] = u0;
+            out2[r * vo2 + p] = fp - Dp * u0 + s;
+        }
+        return;
+    }
+    const cplx<T>* u = a.u[slot];
+    const int64_t vu = a.vu[slot];
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx<T>* ur = u + r * vu;
+        const cplx<T> up = ur[p];
+        const cplx<T> off = c.offsum(d, i, j, k, p, ur);
+        if (MODE == 1) {
+            const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
+            out[r * vo + p] = up + sc * (f[r * vf + p] - Dp * up + off);
+        } else if (MODE == 2) {
+            out[r * vo + p] = f[r * vf + p] - Dp * up + off;
+        } else {
+            out[r * vo + p] = Dp * up - off;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarse levels (stored Galerkin stencils)
+
+template <class T, int WX, int WY, int WZ, int MODE>
+__device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const Dims& d, int i, int j, int k,
+                                             int64_t p, int64_t sy, int64_t sz, int nrhs) {
+    const int64_t np = d.np();
+    constexpr int NX = 2 * WX + 1, NY = 2 * WY + 1;
+    constexpr int CENTRE = (WZ * NY + WY) * NX + WX;
+    const cplx<T>* coef = a.coef[slot];
+    const cplx<T>* f = a.f[slot];
+    cplx<T>* out = a.out[slot];
+    const int64_t vf = a.vf[slot], vo = a.vo[slot];
+    const T damp = a.damp;
+    const cplx<T> Dp = coef[CENTRE * np + p];
+    const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
+    if (MODE == 0) {
+        for (int r = 0; r < nrhs; ++r) out[r * vo + p] = sc * f[r * vf + p];
+        return;
+    }
+    const cplx<T>* u = a.u[slot];
+    const int64_t vu = a.vu[slot];
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx<T>* ur = u + r * vu;
+        const cplx<T>* fr = f + r * vf;
+        cplx<T> xu = czero<T>();
+#pragma unroll
+        for (int oz = -WZ; oz <= WZ; ++oz) {
+            if (k + oz < 0 || k + oz >= d.g[2]) continue;
+#pragma unroll
+            for (int oy = -WY; oy <= WY; ++oy) {
+                if (j + oy < 0 || j + oy >= d.g[1]) continue;
+#pragma unroll
+                for (int ox = -WX; ox <= WX; ++ox) {
+                    if (i + ox < 0 || i + ox >= d.g[0]) continue;
+                    const int o = ((oz + WZ) * NY + (oy + WY)) * NX + (ox + WX);
+                    const int64_t q = p + oz * sz + oy * sy + ox;
+                    cplx<T> v;
+                    if (MODE == 4) v = cdiv(mk<T>(damp, T(0)), coef[CENTRE * np + q]) * fr[q];
+                    else v = ur[q];
+                    xu = xu + coef[o * np + p] * v;
+                }
+            }
+        }
+        if (MODE == 1) {
+            out[r * vo + p] = ur[p] + sc * (fr[p] - xu);
+        } else if (MODE == 2) {
+            out[r * vo + p] = fr[p] - xu;
+        } else if (MODE == 3) {
+            out[r * vo + p] = xu;
+        } else {
+            out[r * vo + p] = sc * fr[p];
+            a.out2[slot][r * a.vo2[slot] + p] = fr[p] - xu;
+        }
+    }
+}
+
+template <class T, int DIM, int MODE>
+__global__ void __launch_bounds__(256)
+k_gstencil(GArgs<T> a, int nrhs) {
+    EH_GROUP_POINT(a, d)
+    const int kind = a.kind[slot];
+    if (DIM == 2) {
+        if (kind == 0) stencil_body<T, 1, 2, 0, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else if (kind == 1) stencil_body<T, 2, 1, 0, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else stencil_body<T, 2, 2, 0, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+    } else {
+        if (kind == 0) stencil_body<T, 1, 2, 2, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else if (kind == 1) stencil_body<T, 2, 1, 2, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else if (kind == 2) stencil_body<T, 2, 2, 1, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else stencil_body<T, 2, 2, 2, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// transfers: restriction (grid = coarse level, reads f as the fine residual,
+// writes out on the coarse grid) and prolongation (grid = fine level, adds P
+// of f (coarse) into out)
+
+template <class T, int DIM, int NM>
+__device__ __forceinline__ void restrict_body(const GArgs<T>& a, int slot, const Dims& dc, int i, int j, int k,
+                                              int64_t p, int nrhs) {
+    using RX = R1<(NM & 1) != 0>;
+    using RY = R1<(NM & 2) != 0>;
+    using RZ = R1<(NM & 4) != 0>;
+    constexpr int SZ = DIM == 3 ? RZ::S : 1;
+    const Dims df = a.dc[slot];      // for restriction dc[] holds the FINE grid
+    const int64_t fsy = df.g[0], fsz = (int64_t)df.g[0] * df.g[1];
+    const int x0 = 2 * i - 1, y0 = 2 * j - 1, z0 = DIM == 3 ? 2 * k - 1 : 0;
+    const cplx<T>* r = a.f[slot];
+    cplx<T>* fc = a.out[slot];
+    const int64_t vsf = a.vf[slot], vsc = a.vo[slot];
+    for (int rr = 0; rr < nrhs; ++rr) {
+        const cplx<T>* rf = r + rr * vsf;
+        cplx<T> s = czero<T>();
+#pragma unroll
+        for (int aa = 0; aa < SZ; ++aa) {
+            const int z = z0 + aa;
+            if (DIM == 3 && (z < 0 || z >= df.g[2])) continue;
+            const T wz = DIM == 3 ? T(RZ::w(aa)) : T(1);
+#pragma unroll
+            for (int b = 0; b < RY::S; ++b) {
+                const int y = y0 + b;
+                if (y < 0 || y >= df.g[1]) continue;
+                const T wzy = wz * T(RY::w(b));
+                const int64_t row = z * fsz + y * fsy;
+#pragma unroll
+                for (int cc = 0; cc < RX::S; ++cc) {
+                    const int x = x0 + cc;
+                    if (x < 0 || x >= df.g[0]) continue;
+                    s = s + (wzy * T(RX::w(cc))) * rf[row + x];
+                }
+            }
+        }
+        fc[rr * vsc + p] = s;
+    }
+}
+
+template <class T, int DIM, int NM>
+__device__ __forceinline__ void prolong_body(const GArgs<T>& a, int slot, const Dims& df, int i, int j, int k,
+                                             int64_t p, int nrhs) {
+    const Dims dc = a.dc[slot];
+    int xi[2], yi[2], zi[2];
+    float xw[2], yw[2], zw[2];
+    p1<(NM & 1) != 0>(i, dc.g[0], xi[0], xi[1], xw[0], xw[1]);
+    p1<(NM & 2) != 0>(j, dc.g[1], yi[0], yi[1], yw[0], yw[1]);
+    if (DIM == 3) p1<(NM & 4) != 0>(k, dc.g[2], zi[0], zi[1], zw[0], zw[1]);
+    else { zi[0] = zi[1] = 0; zw[0] = 1.0f; zw[1] = 0.0f; }
+    const int64_t csy = dc.g[0], csz = (int64_t)dc.g[0] * dc.g[1];
+    const cplx<T>* ec = a.f[slot];
+    cplx<T>* u = a.out[slot];
+    const int64_t vsc = a.vf[slot], vsf = a.vo[slot];
+    for (int rr = 0; rr < nrhs; ++rr) {
+        const cplx<T>* e = ec + rr * vsc;
+        cplx<T> s = czero<T>();
+#pragma unroll
+        for (int aa = 0; aa < (DIM == 3 ? 2 : 1); ++aa)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const T wzy = T(zw[aa]) * T(yw[b]);
+                const int64_t row = zi[aa] * csz + yi[b] * csy;
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) s = s + (wzy * T(xw[cc])) * e[row + xi[cc]];
+            }
+        u[rr * vsf + p] = u[rr * vsf + p] + s;
+    }
+}
+
+template <class T, int DIM, bool RESTRICT>
+__global__ void __launch_bounds__(256)
+k_gtransfer(GArgs<T> a, int nrhs) {
+    EH_GROUP_POINT(a, d)
+    const int kind = a.kind[slot];
+#define EH_TB(NM)                                                      \
+    if (RESTRICT) restrict_body<T, DIM, NM>(a, slot, d, i, j, k, p, nrhs); \
+    else prolong_body<T, DIM, NM>(a, slot, d, i, j, k, p, nrhs);
+    if (kind == DIM) { EH_TB(0) }
+    else if (kind == 0) { EH_TB(1) }
+    else if (kind == 1) { EH_TB(2) }
+    else { EH_TB(4) }
+#undef EH_TB
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: e = Ainv f per slot (one wavefront per row)
+
+struct DenseArgs {
+    int ns;
+    int N[GMAX];
+    const c128* Ainv[GMAX];
+};
+
+template <class T, int RB>
+__global__ void __launch_bounds__(256)
+k_gdense(DenseArgs da, GArgs<T> a) {
+    const int slot = blockIdx.y;
+    if (slot >= da.ns) return;
+    const int N = da.N[slot];
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= N) return;
+    const c128* A = da.Ainv[slot] + (int64_t)row * N;
+    const cplx<T>* f = a.f[slot];
+    cplx<T>* e = a.out[slot];
+    const int64_t vf = a.vf[slot], ve = a.vo[slot];
+    double accr[RB], acci[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) { accr[r] = 0.0; acci[r] = 0.0; }
+    for (int c = lane; c < N; c += 64) {
+        const c128 av = A[c];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const cplx<T> fv = f[r * vf + c];
+            accr[r] += av.re * double(fv.re) - av.im * double(fv.im);
+            acci[r] += av.re * double(fv.im) + av.im * double(fv.re);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        for (int off = 32; off > 0; off >>= 1) {
+            accr[r] += __shfl_xor(accr[r], off, 64);
+            acci[r] += __shfl_xor(acci[r], off, 64);
+        }
+        if (lane == 0) e[r * ve + row] = mk<T>(T(accr[r]), T(acci[r]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coupling g_k = r_k - B_k^T e_p for every shear block (eq. prec)
+
+struct CoupleArgs {
+    int ns;
+    int kind[GMAX];
+    int maxg2;
+    Dims d[GMAX];
+    const c128* ru[GMAX];
+    void* g[GMAX];
+    int64_t vg[GMAX];
+    double ih[GMAX];
+};
+
+template <class T>
+__global__ void __launch_bounds__(256)
+k_gcouple(CoupleArgs a, Dims dc, const cplx<T>* __restrict__ ep, int nrhs, int64_t vr, int64_t ve) {
+    EH_GROUP_POINT(a, d)
+    const int kaxis = a.kind[slot];
+    int c[3] = {i, j, k};
+    const int ck = c[kaxis];
+    int64_t chi = -1, clo = -1;
+    if (ck < dc.g[kaxis]) chi = ((int64_t)c[2] * dc.g[1] + c[1]) * dc.g[0] + c[0];
+    if (ck >= 1) {
+        c[kaxis] = ck - 1;
+        clo = ((int64_t)c[2] * dc.g[1] + c[1]) * dc.g[0] + c[0];
+    }
+    const c128* ru = a.ru[slot];
+    cplx<T>* g = (cplx<T>*)a.g[slot];
+    const double ihk = a.ih[slot];
+    const int64_t vg = a.vg[slot];
+    for (int r = 0; r < nrhs; ++r) {
+        c128 gr = mk(0.0, 0.0);
+        if (chi >= 0) gr = gr + ccast<double>(ep[r * ve + chi]);
+        if (clo >= 0) gr = gr - ccast<double>(ep[r * ve + clo]);
+        g[r * vg + p] = ccast<T>(ru[r * vr + p] - ihk * gr);
+    }
+}
+
+}  // namespace eh

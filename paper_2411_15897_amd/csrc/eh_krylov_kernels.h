@@ -13,86 +13,140 @@ namespace eh {
 constexpr int KRY_THREADS = 256;
 constexpr int KRY_MAXM = 32;   // columns handled by one pass
 
-// Block-wide sum of a double across 256 threads (4 wavefronts).
-__device__ __forceinline__ double block_sum(double v, double* lds) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) lds[w] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) s = lds[0] + lds[1] + lds[2] + lds[3];
-    return s;
-}
-
 // MODE 0: partial[i] = sum_p conj(V_i[p]) w[p]                   (i < m)
 // MODE 1: w <- w - sum_i c_i V_i;  partial[i] = sum conj(V_i) w   (update + dot)
 // MODE 2: w <- w - sum_i c_i V_i;  partial[0] = sum |w|^2          (update + norm)
 // MODE 3: partial[0] = sum |w|^2
-// grid: (nblk, nrhs); partial layout [r][blk][i] (i < m, or 1 for norms).
-// coef layout [r][i] (device).
+// MODE 4: partial[i] = sum conj(V_i) w and partial[m + i] = sum conj(V_i) V_{m-1}
+//         (projections of w and the newest column of the Gram matrix V^H V)
+// grid: (nblk, nrhs); block b owns the KRY_E * 256 entries starting at
+// b * KRY_E * 256 (each thread KRY_E of them, 256 apart: coalesced).
+// partial layout [r][blk][i] (i < m, or 1 for norms); coef layout [r][i].
+constexpr int KRY_E = 4;
 template <int MODE>
 __global__ void __launch_bounds__(KRY_THREADS)
 k_gs(int64_t n, int m, int nrhs, const c128* __restrict__ V, c128* __restrict__ w,
      const c128* __restrict__ coef, c128* __restrict__ partial) {
-    __shared__ double lds[4];
+    __shared__ double lre[4][2 * KRY_MAXM], lim[4][2 * KRY_MAXM];
     const int r = blockIdx.y;
     const int nblk = gridDim.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * (KRY_E * KRY_THREADS) + threadIdx.x;
     c128* wr = w + (int64_t)r * n;
-    double accr[KRY_MAXM], acci[KRY_MAXM];
-    c128 cf[KRY_MAXM];
+    c128 wv[KRY_E];
 #pragma unroll
-    for (int t = 0; t < KRY_MAXM; ++t) {
-        accr[t] = 0.0; acci[t] = 0.0;
-        cf[t] = (MODE == 1 || MODE == 2) && t < m ? coef[r * m + t] : mk(0.0, 0.0);
+    for (int e = 0; e < KRY_E; ++e) {
+        const int64_t p = base + e * KRY_THREADS;
+        wv[e] = p < n ? wr[p] : mk(0.0, 0.0);
     }
-    const int64_t stride = (int64_t)nblk * KRY_THREADS;
-    for (int64_t p = (int64_t)blockIdx.x * KRY_THREADS + threadIdx.x; p < n; p += stride) {
-        c128 wv = wr[p];
-        if (MODE == 1 || MODE == 2) {
+    if (MODE == 1 || MODE == 2) {
+        for (int t = 0; t < m; ++t) {
+            const c128 cf = coef[r * m + t];
+            const c128* Vt = V + ((int64_t)t * nrhs + r) * n;
 #pragma unroll
-            for (int t = 0; t < KRY_MAXM; ++t) {
-                if (t < m) wv = wv - cf[t] * V[((int64_t)t * nrhs + r) * n + p];
+            for (int e = 0; e < KRY_E; ++e) {
+                const int64_t p = base + e * KRY_THREADS;
+                if (p < n) wv[e] = wv[e] - cf * Vt[p];
             }
-            wr[p] = wv;
         }
-        if (MODE == 0 || MODE == 1) {
 #pragma unroll
-            for (int t = 0; t < KRY_MAXM; ++t) {
-                if (t < m) {
-                    const c128 v = V[((int64_t)t * nrhs + r) * n + p];
-                    accr[t] += v.re * wv.re + v.im * wv.im;
-                    acci[t] += v.re * wv.im - v.im * wv.re;
+        for (int e = 0; e < KRY_E; ++e) {
+            const int64_t p = base + e * KRY_THREADS;
+            if (p < n) wr[p] = wv[e];
+        }
+    }
+    int mm = 1;
+    if (MODE == 4) {
+        mm = 2 * m;
+        c128 vl[KRY_E];
+        const c128* Vl = V + ((int64_t)(m - 1) * nrhs + r) * n;
+#pragma unroll
+        for (int e = 0; e < KRY_E; ++e) {
+            const int64_t p = base + e * KRY_THREADS;
+            vl[e] = p < n ? Vl[p] : mk(0.0, 0.0);
+        }
+        for (int t = 0; t < m; ++t) {
+            const c128* Vt = V + ((int64_t)t * nrhs + r) * n;
+            double ar = 0.0, ai = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+            for (int e = 0; e < KRY_E; ++e) {
+                const int64_t p = base + e * KRY_THREADS;
+                if (p < n) {
+                    const c128 v = Vt[p];
+                    ar += v.re * wv[e].re + v.im * wv[e].im;
+                    ai += v.re * wv[e].im - v.im * wv[e].re;
+                    gr += v.re * vl[e].re + v.im * vl[e].im;
+                    gi += v.re * vl[e].im - v.im * vl[e].re;
                 }
             }
-        } else {
-            accr[0] += wv.re * wv.re + wv.im * wv.im;
+            for (int off = 32; off > 0; off >>= 1) {
+                ar += __shfl_xor(ar, off, 64);
+                ai += __shfl_xor(ai, off, 64);
+                gr += __shfl_xor(gr, off, 64);
+                gi += __shfl_xor(gi, off, 64);
+            }
+            if (lane == 0) {
+                lre[wave][t] = ar; lim[wave][t] = ai;
+                lre[wave][m + t] = gr; lim[wave][m + t] = gi;
+            }
         }
-    }
-    const int mm = (MODE == 0 || MODE == 1) ? m : 1;
-    for (int t = 0; t < mm; ++t) {
-        double sr = 0.0, si = 0.0;
+    } else if (MODE == 0 || MODE == 1) {
+        mm = m;
+        for (int t = 0; t < m; ++t) {
+            const c128* Vt = V + ((int64_t)t * nrhs + r) * n;
+            double ar = 0.0, ai = 0.0;
 #pragma unroll
-        for (int q = 0; q < KRY_MAXM; ++q) if (q == t) { sr = accr[q]; si = acci[q]; }
-        sr = block_sum(sr, lds);
-        si = block_sum(si, lds);
-        if (threadIdx.x == 0) partial[((int64_t)r * nblk + blockIdx.x) * mm + t] = mk(sr, si);
+            for (int e = 0; e < KRY_E; ++e) {
+                const int64_t p = base + e * KRY_THREADS;
+                if (p < n) {
+                    const c128 v = Vt[p];
+                    ar += v.re * wv[e].re + v.im * wv[e].im;
+                    ai += v.re * wv[e].im - v.im * wv[e].re;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                ar += __shfl_xor(ar, off, 64);
+                ai += __shfl_xor(ai, off, 64);
+            }
+            if (lane == 0) { lre[wave][t] = ar; lim[wave][t] = ai; }
+        }
+    } else {
+        double a = 0.0;
+#pragma unroll
+        for (int e = 0; e < KRY_E; ++e) a += wv[e].re * wv[e].re + wv[e].im * wv[e].im;
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        if (lane == 0) { lre[wave][0] = a; lim[wave][0] = 0.0; }
+    }
+    __syncthreads();
+    if (threadIdx.x < mm) {
+        const int t = threadIdx.x;
+        const double sr = (lre[0][t] + lre[1][t]) + (lre[2][t] + lre[3][t]);
+        const double si = (lim[0][t] + lim[1][t]) + (lim[2][t] + lim[3][t]);
+        partial[((int64_t)r * nblk + blockIdx.x) * mm + t] = mk(sr, si);
     }
 }
 
-// out[r][i] = sum_blk partial[r][blk][i] in block order; also out2 = out
-// accumulated into acc[r][i] when acc != nullptr.
-__global__ void k_reduce_partials(int nblk, int m, int nrhs, const c128* __restrict__ partial,
-                                  c128* __restrict__ out) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nrhs * m) return;
-    const int r = t / m, i = t % m;
-    double sr = 0.0, si = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+// out[r][i] = sum_blk partial[r][blk][i]: one block per (i, r), fixed-order
+// tree, so the result does not depend on timing.
+__global__ void __launch_bounds__(256)
+k_reduce_partials(int nblk, int m, int nrhs, const c128* __restrict__ partial, c128* __restrict__ out) {
+    __shared__ double sre[256], sim[256];
+    const int i = blockIdx.x, r = blockIdx.y;
+    double ar = 0.0, ai = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) {
         const c128 v = partial[((int64_t)r * nblk + b) * m + i];
-        sr += v.re; si += v.im;
+        ar += v.re; ai += v.im;
     }
-    out[t] = mk(sr, si);
+    sre[threadIdx.x] = ar; sim[threadIdx.x] = ai;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sre[threadIdx.x] += sre[threadIdx.x + s];
+            sim[threadIdx.x] += sim[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[r * m + i] = mk(sre[0], sim[0]);
 }
 
 // v[r] = s[r] * w[r]

@@ -8,7 +8,6 @@
 //  k_distribute: t = B r_u - A_p r_p (eq. mixed-distributed) with
 //      A_p r = B B^T (mu r) - w^2 rho (1 - i gamma/w) r (eq. Ap), written in
 //      the multigrid precision.
-//  k_couple: g_k = r_k - B_k^T e_p (the second block row of eq. prec).
 //
 // Same launch shape as the multigrid kernels.
 #pragma once
@@ -125,21 +124,6 @@ k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
         const c128 Apr = lap - om2 * (mc * pc);
         const c128 tv = mk(-div.re - Apr.re, -div.im - Apr.im);
         t[r * vs_out + p] = ccast<T>(tv);
-    }
-}
-
-template <class T, int DIM>
-__global__ void __launch_bounds__(256)
-k_couple(Dims d, Dims dc, int kaxis, const c128* __restrict__ ru, const cplx<T>* __restrict__ ep,
-         double ihk, cplx<T>* __restrict__ g, int nrhs, int64_t vs_r, int64_t vs_e, int64_t vs_g) {
-    EH_POINT_INDEX(d)
-    const int64_t chi = face_cell(dc, kaxis, i, j, k, 0);
-    const int64_t clo = face_cell(dc, kaxis, i, j, k, -1);
-    for (int r = 0; r < nrhs; ++r) {
-        c128 gr = mk(0.0, 0.0);
-        if (chi >= 0) gr = gr + ccast<double>(ep[r * vs_e + chi]);
-        if (clo >= 0) gr = gr - ccast<double>(ep[r * vs_e + clo]);
-        g[r * vs_g + p] = ccast<T>(ru[r * vs_r + p] - ihk * gr);
     }
 }
 

@@ -20,6 +20,7 @@
 #include "eh_op_kernels.h"
 #include "eh_setup_kernels.h"
 #include "eh_grad_kernels.h"
+#include "eh_group_kernels.h"
 
 using namespace eh;
 
@@ -78,6 +79,22 @@ unsigned lin_grid(int64_t n, int threads = 256, int64_t cap = 65535) {
 
 }  // namespace
 
+// Kernel classes for the event timer (eh_timer_enable / eh_timer_read).
+enum KernelClass {
+    KC_FINE_SWEEP = 0,   // fine-level damped Jacobi sweep (matrix-free)
+    KC_FINE_RESID = 1,   // fine-level residual
+    KC_COARSE = 2,       // coarse-level stencil sweeps / residuals (Galerkin)
+    KC_RESTRICT = 3,
+    KC_PROLONG = 4,
+    KC_DENSE = 5,        // coarsest dense solve
+    KC_OPERATOR = 6,     // y = H x
+    KC_DISTRIBUTE = 7,
+    KC_COUPLE = 8,
+    KC_KRYLOV = 9,       // Gram-Schmidt, scaling, x update
+    KC_FINE_FIRST = 10,  // fine-level first sweep from a zero guess
+    KC_COUNT = 11
+};
+
 struct eh_ctx {
     int dim = 2;
     int64_t n[3] = {1, 1, 1};
@@ -118,6 +135,11 @@ struct eh_ctx {
     std::vector<void*> allocs;
     std::string err;
     bool broken = false;
+    // event timing of selected kernel classes (eh_timer_enable / eh_timer_read)
+    unsigned timer_mask = 0;
+    struct TimerRec { int cls; hipEvent_t a, b; double bytes; };
+    std::vector<TimerRec> timer_recs;
+    std::vector<hipEvent_t> event_pool;
 
     template <class P>
     P* alloc(size_t count) {
@@ -139,6 +161,40 @@ struct eh_ctx {
 };
 
 namespace {
+
+hipEvent_t take_event(eh_ctx* c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+// Records a start event before and a stop event after the launches in its
+// scope when the class is selected; `bytes` is the algorithmic traffic.
+struct Timed {
+    eh_ctx* c;
+    int cls;
+    double bytes;
+    bool on;
+    hipEvent_t a{}, b{};
+    Timed(eh_ctx* c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
+        on = (c->timer_mask >> cls) & 1u;
+        if (on) {
+            a = take_event(c);
+            b = take_event(c);
+            HIPCHK(hipEventRecord(a, c->s));
+        }
+    }
+    ~Timed() {
+        if (!on) return;
+        if (hipEventRecord(b, c->s) == hipSuccess) c->timer_recs.push_back({cls, a, b, bytes});
+        else c->broken = true;     // reported by the next call
+    }
+};
 
 // ---------------------------------------------------------------------------
 // setup on the host (FP64)
@@ -416,168 +472,268 @@ void ensure_tmpT(eh_ctx* c, int64_t elems) {
 }
 
 // ---------------------------------------------------------------------------
-// multigrid cycle (Algorithm TwoCycle, recursive; V: one call, W: two)
+// multigrid cycle (Algorithm TwoCycle, recursive; V: one call, W: two), run
+// for a group of blocks at once (the shear blocks together, H_p alone)
 
 template <class T>
-void launch_op(eh_ctx* c, const Block& B, int l, int mode, const void* f, int64_t vf, const void* u,
-               int64_t vu, void* out, int64_t vo, double damp, int nrhs) {
-    const Level& L = B.lev[l];
-    const dim3 g = grid_of(L.d);
-    const T dmp = T(damp);
-    const cplx<T>* F = (const cplx<T>*)f;
-    const cplx<T>* U = (const cplx<T>*)u;
-    cplx<T>* O = (cplx<T>*)out;
+GArgs<T> gbase(eh_ctx* c, const int* kinds, int ns, int l, bool coarse_dims_for_dc) {
+    GArgs<T> a{};
+    a.ns = ns;
+    a.maxg2 = 1;
+    for (int s = 0; s < ns; ++s) {
+        const Block& B = c->blk[kinds[s]];
+        a.kind[s] = kinds[s];
+        a.d[s] = B.lev[l].d;
+        if (coarse_dims_for_dc && l + 1 < (int)B.lev.size()) a.dc[s] = B.lev[l + 1].d;
+        a.maxg2 = std::max(a.maxg2, a.d[s].g[2]);
+        if (l == 0) {
+            for (int ax = 0; ax < 3; ++ax) a.w[s][ax] = (const T*)B.fw[ax];
+            a.D[s] = (const cplx<T>*)B.fD;
+        } else {
+            a.coef[s] = (const cplx<T>*)B.lev[l].coef;
+        }
+    }
+    a.damp = T(c->blk[kinds[0]].lev[l].damp);
+    for (int ax = 0; ax < 3; ++ax) a.ih[ax] = T(1.0 / (c->h[ax] * c->h[ax]));
+    return a;
+}
+
+template <class T>
+dim3 ggrid(const GArgs<T>& a) {
+    int gx = 1, gy = 1;
+    for (int s = 0; s < a.ns; ++s) {
+        gx = std::max(gx, (a.d[s].g[0] + 63) / 64);
+        gy = std::max(gy, (a.d[s].g[1] + 3) / 4);
+    }
+    return dim3((unsigned)gx, (unsigned)gy, (unsigned)(a.maxg2 * a.ns));
+}
+
+// One sweep-type launch (modes of k_gfine / k_gstencil) on level l.
+template <class T>
+void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
+    const int kind0 = a.kind[0];
+    const bool P = kind0 == c->dim;
+    double by = 0.0;
+    for (int s = 0; s < a.ns; ++s) {
+        const Block& B = c->blk[a.kind[s]];
+        const double np = (double)a.d[s].np(), cs = sizeof(cplx<T>), rs = sizeof(T);
+        double coefb = l == 0 ? np * (cs + (P ? 1 : c->dim) * rs) : np * B.lev[l].w.nst() * cs;
+        double vecb = (mode == 0 || mode == 3) ? 2 * np * cs : (mode == 4 ? 3 * np * cs : 3 * np * cs);
+        if (mode == 0) coefb = np * cs;
+        by += coefb + nrhs * vecb;
+    }
+    const int cls = l > 0 ? KC_COARSE
+                          : (mode == 0 || mode == 4 ? KC_FINE_FIRST : (mode == 1 ? KC_FINE_SWEEP : KC_FINE_RESID));
+    Timed tm(c, cls, by);
+    const dim3 g = ggrid(a);
     if (l == 0) {
-        const T* w0 = (const T*)B.fw[0];
-        const T* w1 = (const T*)B.fw[1];
-        const T* w2 = (const T*)B.fw[2];
-        const T ih0 = T(1.0 / (c->h[0] * c->h[0])), ih1 = T(1.0 / (c->h[1] * c->h[1]));
-        const T ih2 = T(1.0 / (c->h[2] * c->h[2]));
-        const cplx<T>* D = (const cplx<T>*)B.fD;
-        const bool P = B.kind == c->dim;
-#define EH_FINE(KIND, DIM, MODE)                                                                   \
-    hipLaunchKernelGGL((k_fine<T, KIND, DIM, MODE>), g, kBlock, 0, c->s, L.d, w0, w1, w2, ih0, ih1, \
-                       ih2, D, F, U, O, dmp, nrhs, vf, vu, vo)
-#define EH_FINE_M(KIND, DIM)                        \
-    switch (mode) {                                 \
-        case 0: EH_FINE(KIND, DIM, 0); break;       \
-        case 1: EH_FINE(KIND, DIM, 1); break;       \
-        case 2: EH_FINE(KIND, DIM, 2); break;       \
-        default: EH_FINE(KIND, DIM, 3); break;      \
+#define EH_GF(KIND, DIM, MODE) hipLaunchKernelGGL((k_gfine<T, KIND, DIM, MODE>), g, kBlock, 0, c->s, a, nrhs)
+#define EH_GF_M(KIND, DIM)                      \
+    switch (mode) {                             \
+        case 0: EH_GF(KIND, DIM, 0); break;     \
+        case 1: EH_GF(KIND, DIM, 1); break;     \
+        case 2: EH_GF(KIND, DIM, 2); break;     \
+        case 3: EH_GF(KIND, DIM, 3); break;     \
+        default: EH_GF(KIND, DIM, 4); break;    \
     }
-        if (c->dim == 2) {
-            if (P) { EH_FINE_M(1, 2) } else { EH_FINE_M(0, 2) }
-        } else {
-            if (P) { EH_FINE_M(1, 3) } else { EH_FINE_M(0, 3) }
-        }
-#undef EH_FINE_M
-#undef EH_FINE
+        if (c->dim == 2) { if (P) { EH_GF_M(1, 2) } else { EH_GF_M(0, 2) } }
+        else { if (P) { EH_GF_M(1, 3) } else { EH_GF_M(0, 3) } }
+#undef EH_GF_M
+#undef EH_GF
     } else {
-        const cplx<T>* cf = (const cplx<T>*)L.coef;
-        const int wx = L.w.w[0], wy = L.w.w[1], wz = L.w.w[2];
-#define EH_ST(WX, WY, WZ, MODE)                                                                        \
-    hipLaunchKernelGGL((k_stencil<T, WX, WY, WZ, MODE>), g, kBlock, 0, c->s, L.d, cf, F, U, O, dmp, nrhs, \
-                       vf, vu, vo)
-#define EH_ST_M(WX, WY, WZ)                         \
-    switch (mode) {                                 \
-        case 0: EH_ST(WX, WY, WZ, 0); break;        \
-        case 1: EH_ST(WX, WY, WZ, 1); break;        \
-        case 2: EH_ST(WX, WY, WZ, 2); break;        \
-        default: EH_ST(WX, WY, WZ, 3); break;       \
+#define EH_GS(DIM, MODE) hipLaunchKernelGGL((k_gstencil<T, DIM, MODE>), g, kBlock, 0, c->s, a, nrhs)
+#define EH_GS_M(DIM)                        \
+    switch (mode) {                         \
+        case 0: EH_GS(DIM, 0); break;       \
+        case 1: EH_GS(DIM, 1); break;       \
+        case 2: EH_GS(DIM, 2); break;       \
+        case 3: EH_GS(DIM, 3); break;       \
+        default: EH_GS(DIM, 4); break;      \
     }
-        if (wz == 0) {
-            if (wx == 1 && wy == 2) { EH_ST_M(1, 2, 0) }
-            else if (wx == 2 && wy == 1) { EH_ST_M(2, 1, 0) }
-            else { EH_ST_M(2, 2, 0) }
-        } else {
-            if (wx == 1) { EH_ST_M(1, 2, 2) }
-            else if (wy == 1) { EH_ST_M(2, 1, 2) }
-            else if (wz == 1) { EH_ST_M(2, 2, 1) }
-            else { EH_ST_M(2, 2, 2) }
-        }
-#undef EH_ST_M
-#undef EH_ST
+        if (c->dim == 2) { EH_GS_M(2) } else { EH_GS_M(3) }
+#undef EH_GS_M
+#undef EH_GS
     }
     HIPCHK(hipGetLastError());
 }
 
 template <class T>
-void dense_apply(eh_ctx* c, const Block& B, const void* f, int64_t vf, void* e, int64_t ve, int nrhs) {
-    const int N = (int)B.Nc;
-    const dim3 g((unsigned)((N + 3) / 4));
-    int r = 0;
-    while (r < nrhs) {
-        const int left = nrhs - r;
-        const cplx<T>* F = (const cplx<T>*)f + (int64_t)r * vf;
-        cplx<T>* E = (cplx<T>*)e + (int64_t)r * ve;
-        if (left >= 8) {
-            hipLaunchKernelGGL((k_dense_apply<T, 8>), g, dim3(256), 0, c->s, N, B.Ainv, F, E, vf, ve);
-            r += 8;
-        } else if (left >= 4) {
-            hipLaunchKernelGGL((k_dense_apply<T, 4>), g, dim3(256), 0, c->s, N, B.Ainv, F, E, vf, ve);
-            r += 4;
-        } else if (left >= 2) {
-            hipLaunchKernelGGL((k_dense_apply<T, 2>), g, dim3(256), 0, c->s, N, B.Ainv, F, E, vf, ve);
-            r += 2;
-        } else {
-            hipLaunchKernelGGL((k_dense_apply<T, 1>), g, dim3(256), 0, c->s, N, B.Ainv, F, E, vf, ve);
-            r += 1;
-        }
-        HIPCHK(hipGetLastError());
-    }
+void gcopy(eh_ctx* c, int ns, const void* const* src, const int64_t* vs, void* const* dst, const int64_t* vd,
+           const int64_t* np, int nrhs) {
+    for (int s = 0; s < ns; ++s)
+        for (int r = 0; r < nrhs; ++r)
+            HIPCHK(hipMemcpyAsync((cplx<T>*)dst[s] + r * vd[s], (const cplx<T>*)src[s] + r * vs[s],
+                                  np[s] * sizeof(cplx<T>), hipMemcpyDeviceToDevice, c->s));
 }
 
+// One cycle on level l for X_l e = f, for the blocks kinds[0..ns).  f[s]
+// has stride vf[s]; the result goes to out[s] (stride vo[s]).  With guess,
+// out[s] holds the initial guess.
 template <class T>
-void copy_strided(eh_ctx* c, const void* src, int64_t vs, void* dst, int64_t vd, int64_t np, int nrhs) {
-    for (int r = 0; r < nrhs; ++r)
-        HIPCHK(hipMemcpyAsync((cplx<T>*)dst + r * vd, (const cplx<T>*)src + r * vs, np * sizeof(cplx<T>),
-                              hipMemcpyDeviceToDevice, c->s));
-}
-
-// One cycle on level l for X_l e = f.  f has stride vf; the result is
-// written to `out` (stride vo).  With guess, `out` holds the initial guess.
-template <class T>
-void cycle(eh_ctx* c, Block& B, int l, const void* f, int64_t vf, void* out, int64_t vo, bool guess,
-           int nrhs) {
-    const int Lv = (int)B.lev.size();
-    Level& L = B.lev[l];
-    const int64_t np = L.d.np();
+void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, const int64_t* vf,
+            void* const* out, const int64_t* vo, bool guess, int nrhs) {
+    const int Lv = (int)c->blk[kinds[0]].lev.size();
+    Level* L[GMAX];
+    int64_t np[GMAX];
+    for (int s = 0; s < ns; ++s) { L[s] = &c->blk[kinds[s]].lev[l]; np[s] = L[s]->d.np(); }
     if (l == Lv - 1) {
-        dense_apply<T>(c, B, f, vf, out, vo, nrhs);
+        GArgs<T> a = gbase<T>(c, kinds, ns, l, false);
+        DenseArgs da{};
+        da.ns = ns;
+        int Nmax = 1;
+        double by = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            const Block& B = c->blk[kinds[s]];
+            da.N[s] = (int)B.Nc;
+            da.Ainv[s] = B.Ainv;
+            Nmax = std::max(Nmax, da.N[s]);
+            by += (double)B.Nc * B.Nc * sizeof(c128) * ((nrhs + 7) / 8) + 2.0 * B.Nc * nrhs * sizeof(cplx<T>);
+        }
+        Timed tm(c, KC_DENSE, by);
+        int r = 0;
+        while (r < nrhs) {
+            for (int s = 0; s < ns; ++s) {
+                a.f[s] = (const cplx<T>*)f[s] + (int64_t)r * vf[s];
+                a.out[s] = (cplx<T>*)out[s] + (int64_t)r * vo[s];
+                a.vf[s] = vf[s];
+                a.vo[s] = vo[s];
+            }
+            const dim3 g((unsigned)((Nmax + 3) / 4), (unsigned)ns);
+            const int left = nrhs - r;
+            if (left >= 8) { hipLaunchKernelGGL((k_gdense<T, 8>), g, dim3(256), 0, c->s, da, a); r += 8; }
+            else if (left >= 4) { hipLaunchKernelGGL((k_gdense<T, 4>), g, dim3(256), 0, c->s, da, a); r += 4; }
+            else if (left >= 2) { hipLaunchKernelGGL((k_gdense<T, 2>), g, dim3(256), 0, c->s, da, a); r += 2; }
+            else { hipLaunchKernelGGL((k_gdense<T, 1>), g, dim3(256), 0, c->s, da, a); r += 1; }
+            HIPCHK(hipGetLastError());
+        }
         return;
     }
     const int nu1 = c->o.nu_pre, nu2 = c->o.nu_post;
-    const double w = L.damp;
-    const void* cur;
-    int64_t vcur;
-    void* bufs[2] = {L.u, L.t};
-    int nb = 0;    // next internal buffer to write
+    const void* cur[GMAX];
+    int64_t vcur[GMAX];
+    int nb = 0;   // next internal buffer: 0 -> u, 1 -> t
+    auto buf = [&](int s, int which) -> void* { return which == 0 ? L[s]->u : L[s]->t; };
+    GArgs<T> a = gbase<T>(c, kinds, ns, l, false);
+    bool have_resid = false;
+    auto sweep = [&](int mode, bool to_out_last) {
+        // one sweep from cur into a fresh buffer (or into out)
+        void* dst[GMAX];
+        int64_t vd[GMAX];
+        bool use_out = to_out_last;
+        for (int s = 0; s < ns; ++s) if (cur[s] == out[s]) use_out = false;
+        int which = nb;
+        if (!use_out) {
+            bool clash = false;
+            for (int s = 0; s < ns; ++s) if (buf(s, which) == cur[s]) clash = true;
+            if (clash) which ^= 1;
+            nb = which ^ 1;
+        }
+        for (int s = 0; s < ns; ++s) {
+            dst[s] = use_out ? out[s] : buf(s, which);
+            vd[s] = use_out ? vo[s] : np[s];
+            a.f[s] = (const cplx<T>*)f[s];
+            a.vf[s] = vf[s];
+            a.u[s] = (const cplx<T>*)cur[s];
+            a.vu[s] = vcur[s];
+            a.out[s] = (cplx<T>*)dst[s];
+            a.vo[s] = vd[s];
+        }
+        gsweep<T>(c, a, l, mode, nrhs);
+        for (int s = 0; s < ns; ++s) { cur[s] = dst[s]; vcur[s] = vd[s]; }
+    };
     if (guess) {
-        cur = out; vcur = vo;
-        for (int s = 0; s < nu1; ++s) {
-            void* dst = bufs[nb]; nb ^= 1;
-            launch_op<T>(c, B, l, 1, f, vf, cur, vcur, dst, np, w, nrhs);
-            cur = dst; vcur = np;
+        for (int s = 0; s < ns; ++s) { cur[s] = out[s]; vcur[s] = vo[s]; }
+        for (int t = 0; t < nu1; ++t) sweep(1, false);
+    } else if (nu1 == 1) {
+        // first sweep fused with the residual
+        for (int s = 0; s < ns; ++s) {
+            a.f[s] = (const cplx<T>*)f[s];
+            a.vf[s] = vf[s];
+            a.out[s] = (cplx<T>*)L[s]->u;
+            a.vo[s] = np[s];
+            a.out2[s] = (cplx<T>*)L[s]->r;
+            a.vo2[s] = np[s];
         }
-    } else if (nu1 > 0) {
-        void* dst = bufs[nb]; nb ^= 1;
-        launch_op<T>(c, B, l, 0, f, vf, nullptr, 0, dst, np, w, nrhs);
-        cur = dst; vcur = np;
-        for (int s = 1; s < nu1; ++s) {
-            void* d2 = bufs[nb]; nb ^= 1;
-            launch_op<T>(c, B, l, 1, f, vf, cur, vcur, d2, np, w, nrhs);
-            cur = d2; vcur = np;
+        gsweep<T>(c, a, l, 4, nrhs);
+        for (int s = 0; s < ns; ++s) { cur[s] = L[s]->u; vcur[s] = np[s]; }
+        nb = 1;
+        have_resid = true;
+    } else if (nu1 > 1) {
+        for (int s = 0; s < ns; ++s) {
+            a.f[s] = (const cplx<T>*)f[s];
+            a.vf[s] = vf[s];
+            a.out[s] = (cplx<T>*)L[s]->u;
+            a.vo[s] = np[s];
         }
+        gsweep<T>(c, a, l, 0, nrhs);
+        for (int s = 0; s < ns; ++s) { cur[s] = L[s]->u; vcur[s] = np[s]; }
+        nb = 1;
+        for (int t = 1; t < nu1; ++t) sweep(1, false);
     } else {
-        HIPCHK(hipMemsetAsync(L.u, 0, (size_t)np * nrhs * sizeof(cplx<T>), c->s));
-        cur = L.u; vcur = np; nb = 1;
-    }
-    // residual, restriction, coarse solve(s), prolongation
-    launch_op<T>(c, B, l, 2, f, vf, cur, vcur, L.r, np, w, nrhs);
-    Level& C = B.lev[l + 1];
-    const int64_t npc = C.d.np();
-    hipLaunchKernelGGL((k_restrict<T>), grid_of(C.d), kBlock, 0, c->s, L.d, C.d, B.nodal_mask,
-                       (const cplx<T>*)L.r, (cplx<T>*)C.f, nrhs, np, npc);
-    HIPCHK(hipGetLastError());
-    const int ncalls = (c->o.cycle == 1) ? 2 : 1;
-    for (int t = 0; t < ncalls; ++t) cycle<T>(c, B, l + 1, C.f, npc, C.e, npc, t > 0, nrhs);
-    // cur may be `out` (guess, nu1 == 0); the update is elementwise, in place
-    hipLaunchKernelGGL((k_prolong_add<T>), grid_of(L.d), kBlock, 0, c->s, L.d, C.d, B.nodal_mask,
-                       (const cplx<T>*)C.e, (cplx<T>*)cur, nrhs, vcur, npc);
-    HIPCHK(hipGetLastError());
-    for (int s = 0; s < nu2; ++s) {
-        void* dst;
-        int64_t vd;
-        if (s == nu2 - 1 && cur != out) { dst = out; vd = vo; }
-        else {
-            dst = bufs[nb]; nb ^= 1;
-            if (dst == cur) { dst = bufs[nb]; nb ^= 1; }
-            vd = np;
+        for (int s = 0; s < ns; ++s) {
+            HIPCHK(hipMemsetAsync(L[s]->u, 0, (size_t)np[s] * nrhs * sizeof(cplx<T>), c->s));
+            cur[s] = L[s]->u; vcur[s] = np[s];
         }
-        launch_op<T>(c, B, l, 1, f, vf, cur, vcur, dst, vd, w, nrhs);
-        cur = dst; vcur = vd;
+        nb = 1;
     }
-    if (cur != out) copy_strided<T>(c, cur, vcur, out, vo, np, nrhs);
+    if (!have_resid) {
+        for (int s = 0; s < ns; ++s) {
+            a.f[s] = (const cplx<T>*)f[s];
+            a.vf[s] = vf[s];
+            a.u[s] = (const cplx<T>*)cur[s];
+            a.vu[s] = vcur[s];
+            a.out[s] = (cplx<T>*)L[s]->r;
+            a.vo[s] = np[s];
+        }
+        gsweep<T>(c, a, l, 2, nrhs);
+    }
+    // restriction onto level l+1 (kernel grid = coarse; dc[] = fine grid)
+    Level* C[GMAX];
+    int64_t npc[GMAX];
+    const void* cf[GMAX];
+    void* ce[GMAX];
+    int64_t vcv[GMAX];
+    {
+        GArgs<T> t = gbase<T>(c, kinds, ns, l + 1, false);
+        double by = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            C[s] = &c->blk[kinds[s]].lev[l + 1];
+            npc[s] = C[s]->d.np();
+            t.dc[s] = L[s]->d;
+            t.f[s] = (const cplx<T>*)L[s]->r;
+            t.vf[s] = np[s];
+            t.out[s] = (cplx<T>*)C[s]->f;
+            t.vo[s] = npc[s];
+            cf[s] = C[s]->f; ce[s] = C[s]->e; vcv[s] = npc[s];
+            by += (double)(np[s] + npc[s]) * nrhs * sizeof(cplx<T>);
+        }
+        Timed tm(c, KC_RESTRICT, by);
+        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, true>), ggrid(t), kBlock, 0, c->s, t, nrhs);
+        else hipLaunchKernelGGL((k_gtransfer<T, 3, true>), ggrid(t), kBlock, 0, c->s, t, nrhs);
+        HIPCHK(hipGetLastError());
+    }
+    const int ncalls = (c->o.cycle == 1) ? 2 : 1;
+    for (int t = 0; t < ncalls; ++t) gcycle<T>(c, kinds, ns, l + 1, cf, vcv, ce, vcv, t > 0, nrhs);
+    // prolongation and correction, in place on cur (elementwise)
+    {
+        GArgs<T> t = gbase<T>(c, kinds, ns, l, true);
+        double by = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            t.f[s] = (const cplx<T>*)C[s]->e;
+            t.vf[s] = npc[s];
+            t.out[s] = (cplx<T>*)cur[s];
+            t.vo[s] = vcur[s];
+            by += (double)(2 * np[s] + npc[s]) * nrhs * sizeof(cplx<T>);
+        }
+        Timed tm(c, KC_PROLONG, by);
+        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, false>), ggrid(t), kBlock, 0, c->s, t, nrhs);
+        else hipLaunchKernelGGL((k_gtransfer<T, 3, false>), ggrid(t), kBlock, 0, c->s, t, nrhs);
+        HIPCHK(hipGetLastError());
+    }
+    for (int t = 0; t < nu2; ++t) sweep(1, t == nu2 - 1);
+    bool need_copy = false;
+    for (int s = 0; s < ns; ++s) if (cur[s] != out[s]) need_copy = true;
+    if (need_copy) gcopy<T>(c, ns, cur, vcur, out, vo, np, nrhs);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,6 +743,9 @@ template <class Tin>
 void apply_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs) {
     const cplx<Tin>* X = (const cplx<Tin>*)x;
     const cplx<Tin>* pf = X + c->off[c->dim];
+    double coefb = 8.0 * c->ncell;
+    for (int k = 0; k < c->dim; ++k) coefb += (double)c->fsize[k] * (8.0 * c->dim + 16.0);
+    Timed tm(c, KC_OPERATOR, coefb + (double)nrhs * c->ndof * (sizeof(cplx<Tin>) + sizeof(c128)));
     for (int k = 0; k < c->dim; ++k) {
         const Dims& d = c->dface[k];
         if (c->dim == 2)
@@ -619,6 +778,8 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
     Block& Bp = c->blk[d];
     Level& Lp = Bp.lev[0];
     const c128* r2 = d == 3 ? r + c->off[2] : r;
+    {
+    Timed tm(c, KC_DISTRIBUTE, 24.0 * c->ncell + (double)nrhs * (c->ndof * 16.0 + c->ncell * sizeof(cplx<T>)));
     if (d == 2)
         hipLaunchKernelGGL((k_distribute<T, 2>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, r + c->off[0],
                            r + c->off[1], r2, r + c->off[d], c->mu, c->mcell, c->omega * c->omega,
@@ -628,22 +789,53 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
                            r + c->off[1], r2, r + c->off[d], c->mu, c->mcell, c->omega * c->omega,
                            1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell);
     HIPCHK(hipGetLastError());
+    }
     cplx<T>* Z = (cplx<T>*)z;
     cplx<T>* ep = Z + c->off[d];
-    cycle<T>(c, Bp, 0, Lp.f, c->ncell, ep, vz, false, nrhs);
-    for (int k = 0; k < d; ++k) {
-        Block& Bk = c->blk[k];
-        Level& Lk = Bk.lev[0];
-        const int64_t np = Lk.d.np();
-        if (d == 2)
-            hipLaunchKernelGGL((k_couple<T, 2>), grid_of(Lk.d), kBlock, 0, c->s, Lk.d, c->dcell, k, r + c->off[k],
-                               (const cplx<T>*)ep, 1.0 / c->h[k], (cplx<T>*)Lk.f, nrhs, vr, vz, np);
-        else
-            hipLaunchKernelGGL((k_couple<T, 3>), grid_of(Lk.d), kBlock, 0, c->s, Lk.d, c->dcell, k, r + c->off[k],
-                               (const cplx<T>*)ep, 1.0 / c->h[k], (cplx<T>*)Lk.f, nrhs, vr, vz, np);
-        HIPCHK(hipGetLastError());
-        cycle<T>(c, Bk, 0, Lk.f, np, Z + c->off[k], vz, false, nrhs);
+    {
+        const int kinds[1] = {d};
+        const void* f[1] = {Lp.f};
+        const int64_t vf[1] = {c->ncell};
+        void* out[1] = {ep};
+        const int64_t vo[1] = {vz};
+        gcycle<T>(c, kinds, 1, 0, f, vf, out, vo, false, nrhs);
     }
+    int kinds[GMAX];
+    const void* f[GMAX];
+    int64_t vf[GMAX], vo[GMAX];
+    void* out[GMAX];
+    CoupleArgs ca{};
+    ca.ns = d;
+    ca.maxg2 = 1;
+    double by = 0.0;
+    for (int k = 0; k < d; ++k) {
+        Level& Lk = c->blk[k].lev[0];
+        kinds[k] = k;
+        f[k] = Lk.f;
+        vf[k] = Lk.d.np();
+        out[k] = Z + c->off[k];
+        vo[k] = vz;
+        ca.kind[k] = k;
+        ca.d[k] = Lk.d;
+        ca.maxg2 = std::max(ca.maxg2, Lk.d.g[2]);
+        ca.ru[k] = r + c->off[k];
+        ca.g[k] = Lk.f;
+        ca.vg[k] = Lk.d.np();
+        ca.ih[k] = 1.0 / c->h[k];
+        by += (double)nrhs * (Lk.d.np() * (16.0 + sizeof(cplx<T>)) + c->ncell * sizeof(cplx<T>));
+    }
+    {
+        Timed tm(c, KC_COUPLE, by);
+        int gx = 1, gy = 1;
+        for (int k = 0; k < d; ++k) {
+            gx = std::max(gx, (ca.d[k].g[0] + 63) / 64);
+            gy = std::max(gy, (ca.d[k].g[1] + 3) / 4);
+        }
+        hipLaunchKernelGGL((k_gcouple<T>), dim3(gx, gy, ca.maxg2 * d), kBlock, 0, c->s, ca, c->dcell,
+                           (const cplx<T>*)ep, nrhs, vr, vz);
+        HIPCHK(hipGetLastError());
+    }
+    gcycle<T>(c, kinds, d, 0, f, vf, out, vo, false, nrhs);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,9 +849,9 @@ void ensure_krylov(eh_ctx* c, int nrhs, int m) {
     c->V = c->alloc<c128>((size_t)(m + 1) * nrhs * c->ndof);
     c->Z = c->alloc<char>((size_t)m * nrhs * c->ndof * c->csize());
     c->W = c->alloc<c128>((size_t)nrhs * c->ndof);
-    c->kry_nblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (c->ndof + 1023) / 1024));
-    c->partial = c->alloc<c128>((size_t)c->kry_nblk * nrhs * (m + 1));
-    c->dsmall = c->alloc<c128>((size_t)4 * nrhs * (m + 2));
+    c->kry_nblk = (int)std::max<int64_t>(1, (c->ndof + KRY_E * KRY_THREADS - 1) / (KRY_E * KRY_THREADS));
+    c->partial = c->alloc<c128>((size_t)c->kry_nblk * nrhs * 2 * (m + 1));
+    c->dsmall = c->alloc<c128>((size_t)5 * nrhs * 2 * (m + 2));
     c->dscale = c->alloc<double>(nrhs);
     c->kry_nrhs = nrhs;
     c->kry_m = m;
@@ -670,12 +862,13 @@ void ensure_krylov(eh_ctx* c, int nrhs, int m) {
 template <int MODE>
 void gs_pass(eh_ctx* c, int m, int nrhs, const c128* V, c128* w, const c128* coef, c128* out) {
     const int nblk = c->kry_nblk;
+    const double vecs = (MODE == 0 || MODE == 4) ? m + 1 : (MODE == 3 ? 1 : m + 2);
+    Timed tm(c, KC_KRYLOV, vecs * nrhs * c->ndof * sizeof(c128));
     hipLaunchKernelGGL((k_gs<MODE>), dim3(nblk, nrhs), dim3(KRY_THREADS), 0, c->s, c->ndof, m, nrhs, V, w,
                        coef, c->partial);
     HIPCHK(hipGetLastError());
-    const int mm = (MODE == 0 || MODE == 1) ? m : 1;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(lin_grid((int64_t)nrhs * mm)), dim3(256), 0, c->s, nblk, mm,
-                       nrhs, c->partial, out);
+    const int mm = (MODE == 0 || MODE == 1) ? m : (MODE == 4 ? 2 * m : 1);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(mm, nrhs), dim3(256), 0, c->s, nblk, mm, nrhs, c->partial, out);
     HIPCHK(hipGetLastError());
 }
 
@@ -691,6 +884,7 @@ void norms(eh_ctx* c, const c128* w, int nrhs, std::vector<double>& out) {
 
 void scale_into(eh_ctx* c, const c128* w, c128* v, const std::vector<double>& s, int nrhs) {
     HIPCHK(hipMemcpyAsync(c->dscale, s.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->s));
+    Timed tm(c, KC_KRYLOV, 2.0 * nrhs * c->ndof * sizeof(c128));
     hipLaunchKernelGGL(k_scale, dim3(lin_grid(c->ndof, 256, 2048), nrhs), dim3(256), 0, c->s, c->ndof, nrhs,
                        c->dscale, w, v);
     HIPCHK(hipGetLastError());
@@ -716,7 +910,8 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
     std::vector<cd> Hh((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), cs((size_t)nrhs * m),
         sn((size_t)nrhs * m);
     std::vector<int> jr(nrhs, 0), active(nrhs, 0);
-    std::vector<c128> h1((size_t)nrhs * m), h2((size_t)nrhs * m), nr(nrhs);
+    std::vector<c128> h1((size_t)nrhs * 2 * m), hcol((size_t)nrhs * m), nr(nrhs);
+    std::vector<cd> Gm((size_t)nrhs * m * m);
     std::vector<c128> ydev((size_t)nrhs * m);
     while (total < maxit) {
         // r = b - H x
@@ -749,15 +944,35 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
             apply_M<T>(c, Vj, n, Zj, n, nrhs);
             apply_H<T>(c, Zj, n, c->W, n, nrhs);
             ++total;
-            // classical Gram-Schmidt, twice
+            // Classical Gram-Schmidt with one reorthogonalisation (CGS2) in two
+            // passes: the first gives h1 = V^H w and the newest Gram column
+            // V^H v_j; the second-pass coefficients follow exactly from
+            // h2 = V^H (w - V h1) = h1 - G h1 with G = V^H V, so the update
+            // w <- w - V (h1 + h2) and ||w|| take one more pass.
             c128* d1 = c->dsmall;
-            c128* d2 = c->dsmall + (size_t)nrhs * (m + 2);
-            c128* d3 = c->dsmall + (size_t)2 * nrhs * (m + 2);
-            gs_pass<0>(c, j + 1, nrhs, c->V, c->W, nullptr, d1);
-            gs_pass<1>(c, j + 1, nrhs, c->V, c->W, d1, d2);
+            c128* d2 = c->dsmall + (size_t)2 * nrhs * (m + 2);
+            c128* d3 = c->dsmall + (size_t)4 * nrhs * (m + 2);
+            gs_pass<4>(c, j + 1, nrhs, c->V, c->W, nullptr, d1);
+            HIPCHK(hipMemcpyAsync(h1.data(), d1, (size_t)nrhs * 2 * (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipStreamSynchronize(c->s));
+            for (int r = 0; r < nrhs; ++r) {
+                const c128* hr = &h1[(size_t)r * 2 * (j + 1)];
+                for (int i = 0; i <= j; ++i)     // Gram column j: G[i][j] = v_i^H v_j
+                    Gm[((size_t)r * m + j) * m + i] = cd(hr[j + 1 + i].re, hr[j + 1 + i].im);
+                for (int i = 0; i <= j; ++i) {
+                    cd gh = 0.0;
+                    for (int q = 0; q <= j; ++q) {
+                        // G[i][q] = v_i^H v_q; stored by column q (q >= i) or conj of column i
+                        const cd gi = (q >= i) ? Gm[((size_t)r * m + q) * m + i]
+                                               : std::conj(Gm[((size_t)r * m + i) * m + q]);
+                        gh += gi * cd(hr[q].re, hr[q].im);
+                    }
+                    const cd tot = 2.0 * cd(hr[i].re, hr[i].im) - gh;
+                    hcol[(size_t)r * (j + 1) + i] = mk(tot.real(), tot.imag());
+                }
+            }
+            HIPCHK(hipMemcpyAsync(d2, hcol.data(), (size_t)nrhs * (j + 1) * sizeof(c128), hipMemcpyHostToDevice, c->s));
             gs_pass<2>(c, j + 1, nrhs, c->V, c->W, d2, d3);
-            HIPCHK(hipMemcpyAsync(h1.data(), d1, (size_t)nrhs * (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipMemcpyAsync(h2.data(), d2, (size_t)nrhs * (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, c->s));
             HIPCHK(hipMemcpyAsync(nr.data(), d3, (size_t)nrhs * sizeof(c128), hipMemcpyDeviceToHost, c->s));
             HIPCHK(hipStreamSynchronize(c->s));
             bool any_active = false;
@@ -766,8 +981,7 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
                 if (!active[r]) continue;
                 cd* col = &Hh[((size_t)r * m + j) * (m + 1)];
                 for (int i = 0; i <= j; ++i)
-                    col[i] = cd(h1[(size_t)r * (j + 1) + i].re + h2[(size_t)r * (j + 1) + i].re,
-                                h1[(size_t)r * (j + 1) + i].im + h2[(size_t)r * (j + 1) + i].im);
+                    col[i] = cd(hcol[(size_t)r * (j + 1) + i].re, hcol[(size_t)r * (j + 1) + i].im);
                 const double hn = std::sqrt(std::max(0.0, nr[r].re));
                 double w0 = 0.0;
                 for (int i = 0; i <= j; ++i) w0 += std::norm(col[i]);
@@ -821,8 +1035,9 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
             for (int i = 0; i < jj; ++i) ydev[(size_t)r * m + i] = mk(y[i].real(), y[i].imag());
         }
         if (mmax > 0) {
-            c128* dy = c->dsmall + (size_t)3 * nrhs * (m + 2);
+            c128* dy = c->dsmall + (size_t)6 * nrhs * (m + 2);
             HIPCHK(hipMemcpyAsync(dy, ydev.data(), (size_t)nrhs * m * sizeof(c128), hipMemcpyHostToDevice, c->s));
+            Timed tm(c, KC_KRYLOV, (double)nrhs * n * (2 * sizeof(c128) + m * sizeof(cplx<T>)));
             hipLaunchKernelGGL((k_xupdate<T>), dim3(lin_grid(n, 256, 2048), nrhs), dim3(256), 0, c->s, n, m, nrhs,
                                (const cplx<T>*)Z, dy, x);
             HIPCHK(hipGetLastError());
@@ -862,6 +1077,10 @@ eh_status from_hip(eh_ctx* c, const HipError& e) {
 }
 
 void destroy_all(eh_ctx* c) {
+    for (auto& r : c->timer_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    c->timer_recs.clear();
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    c->event_pool.clear();
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
 }
@@ -1058,6 +1277,37 @@ void eh_destroy(eh_ctx* c) {
     delete c;
 }
 
+eh_status eh_timer_enable(eh_ctx* c, unsigned class_mask) {
+    if (!c || class_mask >= (1u << KC_COUNT)) return EH_ERR_ARG;
+    c->timer_mask = class_mask;
+    return EH_OK;
+}
+
+eh_status eh_timer_read(eh_ctx* c, int cls, int64_t* launches, double* ms, double* bytes) {
+    if (!c || cls < 0 || cls >= KC_COUNT || !launches || !ms || !bytes) return EH_ERR_ARG;
+    try {
+        int64_t cnt = 0;
+        double t = 0.0, by = 0.0;
+        std::vector<eh_ctx::TimerRec> keep;
+        for (auto& r : c->timer_recs) {
+            if (r.cls != cls) { keep.push_back(r); continue; }
+            HIPCHK(hipEventSynchronize(r.b));
+            float e = 0.f;
+            HIPCHK(hipEventElapsedTime(&e, r.a, r.b));
+            t += e;
+            by += r.bytes;
+            ++cnt;
+            c->event_pool.push_back(r.a);
+            c->event_pool.push_back(r.b);
+        }
+        c->timer_recs.swap(keep);
+        *launches = cnt;
+        *ms = t;
+        *bytes = by;
+    } catch (const HipError& e) { return from_hip(c, e); }
+    return EH_OK;
+}
+
 eh_status eh_set_stream(eh_ctx* c, void* stream) {
     if (!c) return EH_ERR_ARG;
     c->s = (hipStream_t)stream;
@@ -1115,7 +1365,11 @@ void block_cycle_T(eh_ctx* c, int block, const void* f, void* e, int nrhs) {
                        (const c128*)f, (cplx<T>*)L.f);
     HIPCHK(hipGetLastError());
     ensure_tmpT(c, tot);
-    cycle<T>(c, B, 0, L.f, np, c->tmpT, np, false, nrhs);
+    const int kinds[1] = {block};
+    const void* fa[1] = {L.f};
+    const int64_t vf[1] = {np};
+    void* out[1] = {c->tmpT};
+    gcycle<T>(c, kinds, 1, 0, fa, vf, out, vf, false, nrhs);
     hipLaunchKernelGGL((k_cast<double, T>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,
                        (const cplx<T>*)c->tmpT, (c128*)e);
     HIPCHK(hipGetLastError());
@@ -1131,7 +1385,13 @@ void block_apply_T(eh_ctx* c, int block, int level, const void* x, void* y, int 
     hipLaunchKernelGGL((k_cast<T, double>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,
                        (const c128*)x, (cplx<T>*)L.u);
     HIPCHK(hipGetLastError());
-    launch_op<T>(c, B, level, 3, nullptr, 0, L.u, np, L.t, np, 1.0, nrhs);
+    const int kinds[1] = {block};
+    GArgs<T> a = gbase<T>(c, kinds, 1, level, false);
+    a.u[0] = (const cplx<T>*)L.u;
+    a.vu[0] = np;
+    a.out[0] = (cplx<T>*)L.t;
+    a.vo[0] = np;
+    gsweep<T>(c, a, level, 3, nrhs);
     hipLaunchKernelGGL((k_cast<double, T>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,
                        (const cplx<T>*)L.t, (c128*)y);
     HIPCHK(hipGetLastError());

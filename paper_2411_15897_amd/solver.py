@@ -189,6 +189,20 @@ class ElasticHelmholtz:
                                         _ptr(g), ctypes.byref(phi)))
         return phi.value, g
 
+    def timer_enable(self, classes):
+        """Select kernel classes (names of _native.KERNEL_CLASSES) to time."""
+        mask = 0
+        for c in classes:
+            mask |= 1 << N.KERNEL_CLASSES[c]
+        self._check(self._lib.eh_timer_enable(self._ctx, mask))
+
+    def timer_read(self, cls):
+        """(launches, milliseconds, algorithmic bytes) since the last read."""
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.eh_timer_read(self._ctx, N.KERNEL_CLASSES[cls], ctypes.byref(n),
+                                            ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value
+
     def gradient(self, u, w):
         nrhs = self._nrhs(u, self.ndof)
         _check_dev(u, torch.complex128, nrhs * self.ndof, "u")
