@@ -65,6 +65,9 @@ typedef struct {
     int abc_width;          /* absorbing layer width in cells (Section 4: 20) */
     unsigned abc_sides;     /* bitmask of absorbing sides: bit 2a low side of axis a, bit 2a+1 high side */
     double gamma0;          /* natural attenuation everywhere (Section 4: 0.01 pi) */
+    int intergrid;          /* 0: full-weighting restriction R = P^T/2^d (eqs. Ru1, Rp);
+                               1: mixed intergrid, (1/2)[1 * 1] along cell-centred axes
+                               (eq. tildeRu1, the paper's 3D setting); P is (bi/tri)linear either way */
 } eh_opts;
 
 typedef struct {
@@ -76,7 +79,8 @@ typedef struct {
 
 /* Fill `opts` with defaults: 3 levels, V(1,2), damping 0.8/0.8/0.3,
  * alpha 0.1, complex64 multigrid, restart 20, 20-cell layer on all sides but
- * the top, gamma0 = 0.01 pi (Sections 4 and 4.4.1). */
+ * the top, gamma0 = 0.01 pi, full-weighting intergrid (Sections 4 and
+ * 4.4.1). */
 void eh_default_opts(eh_opts *opts);
 
 /* Set up the operator and the preconditioner for one grid, medium and

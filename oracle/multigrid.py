@@ -56,16 +56,41 @@ def prolong_1d(nc, nodal):
     return sp.csr_matrix((vals, (rows, cols)), shape=shape)
 
 
-def transfer(n_fine, nodal):
+def restrict_mixed_1d(nc, nodal):
+    """1D restriction of the mixed intergrid (eq. tildeRu1): along a nodal
+    axis (1/4)[1 2 1] as in full weighting, along a cell-centred axis
+    (1/2)[1 * 1], the mean of the two fine cells 2I and 2I+1."""
+    rows, cols, vals = [], [], []
+    if nodal:
+        for I in range(nc + 1):
+            for f, w in ((2 * I - 1, 0.25), (2 * I, 0.5), (2 * I + 1, 0.25)):
+                if 0 <= f <= 2 * nc:
+                    rows.append(I); cols.append(f); vals.append(w)
+        shape = (nc + 1, 2 * nc + 1)
+    else:
+        for I in range(nc):
+            rows += [I, I]; cols += [2 * I, 2 * I + 1]; vals += [0.5, 0.5]
+        shape = (nc, 2 * nc)
+    return sp.csr_matrix((vals, (rows, cols)), shape=shape)
+
+
+def transfer(n_fine, nodal, intergrid="full"):
     """(P, R) between the grid with n_fine cells per axis and the grid with
     half as many; `nodal[a]` says whether the block's unknowns are nodal
-    along axis a.  R = P^T / 2^d."""
+    along axis a.  P is (bi/tri)linear interpolation.  intergrid "full":
+    R = P^T / 2^d (eqs. Ru1, Rp); "mixed": R is the Kronecker product of the
+    1D restrictions of eq. tildeRu1 (the paper's 3D setting, Section 4.5)."""
     d = len(n_fine)
     for v in n_fine:
         if v % 2:
             raise ValueError("grid not divisible by 2")
     P = kron_axes([prolong_1d(n_fine[a] // 2, nodal[a]) for a in range(d)])
-    R = (P.T / (2.0 ** d)).tocsr()
+    if intergrid == "full":
+        R = (P.T / (2.0 ** d)).tocsr()
+    elif intergrid == "mixed":
+        R = kron_axes([restrict_mixed_1d(n_fine[a] // 2, nodal[a]) for a in range(d)])
+    else:
+        raise ValueError(intergrid)
     return P, R
 
 
@@ -73,14 +98,14 @@ class Hierarchy:
     """Galerkin hierarchy of one block X on `levels` grids."""
 
     def __init__(self, X, n, nodal, levels, damping=(0.8, 0.8, 0.3),
-                 nu=(1, 2), cycle="V"):
+                 nu=(1, 2), cycle="V", intergrid="full"):
         if levels < 1:
             raise ValueError("levels >= 1")
         self.ops = [sp.csr_matrix(X)]
         self.P, self.R = [], []
         nl = tuple(n)
         for _ in range(levels - 1):
-            P, R = transfer(nl, nodal)
+            P, R = transfer(nl, nodal, intergrid)
             self.P.append(P)
             self.R.append(R)
             self.ops.append((R @ self.ops[-1] @ P).tocsr())

@@ -30,7 +30,7 @@ from .multigrid import Hierarchy
 class BlockAcoustic:
     def __init__(self, sys: ElasticSystem, alpha=0.0, solver="mg", levels=3,
                  cycle="V", nu=(1, 2), damping=(0.8, 0.8, 0.3),
-                 tilde_Ap=False):
+                 tilde_Ap=False, intergrid="full"):
         self.sys = sys
         d = sys.dim
         self.Ap = sys.A_p_tilde() if tilde_Ap else sys.A_p()
@@ -46,9 +46,10 @@ class BlockAcoustic:
             self.solve_u = [lu.solve for lu in lu_u]
         elif solver == "mg":
             cell = tuple(False for _ in range(d))
-            self.mg_p = Hierarchy(Hp, sys.n, cell, levels, damping, nu, cycle)
+            self.mg_p = Hierarchy(Hp, sys.n, cell, levels, damping, nu, cycle,
+                                  intergrid)
             self.mg_u = [Hierarchy(blocks[k], sys.n, face_nodal(d, k), levels,
-                                   damping, nu, cycle) for k in range(d)]
+                                   damping, nu, cycle, intergrid) for k in range(d)]
             self.solve_p = self.mg_p
             self.solve_u = list(self.mg_u)
         else:

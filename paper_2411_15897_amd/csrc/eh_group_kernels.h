@@ -39,8 +39,10 @@ struct GArgs {
     const T* w[GMAX][3];     // fine-level couplings
     const cplx<T>* D[GMAX];  // fine-level diagonal
     const cplx<T>* coef[GMAX];   // coarse-level stencil
+    const cplx<T>* dinv[GMAX];   // coarse level: damping / diagonal per point
     T damp;
     T ih[3];                 // 1 / h_a^2
+    int mixed;               // mixed intergrid (27-point coarse stencils)
 };
 
 #define EH_GROUP_POINT(a, DD)                                                   \
@@ -62,66 +64,75 @@ template <class T, int KIND, int DIM, int MODE>
 __global__ void __launch_bounds__(256)
 k_gfine(GArgs<T> a, int nrhs) {
     EH_GROUP_POINT(a, d)
-    const T* w0 = a.w[slot][0];
-    const T* w1 = a.w[slot][1];
-    const T* w2 = a.w[slot][2];
-    const cplx<T>* D = a.D[slot];
-    const cplx<T>* f = a.f[slot];
-    cplx<T>* out = a.out[slot];
+    const T* __restrict__ w0 = a.w[slot][0];
+    const T* __restrict__ w1 = a.w[slot][1];
+    const T* __restrict__ w2 = a.w[slot][2];
+    const cplx<T>* __restrict__ D = a.D[slot];
+    const cplx<T>* __restrict__ f = a.f[slot];
+    cplx<T>* __restrict__ out = a.out[slot];
     const int64_t vf = a.vf[slot], vo = a.vo[slot];
     const cplx<T> Dp = D[p];
     const T damp = a.damp;
+    const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
     if (MODE == 0) {
-        const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
         for (int r = 0; r < nrhs; ++r) out[r * vo + p] = sc * f[r * vf + p];
         return;
     }
     FineCoef<T, KIND, DIM> c;
     c.load(d, i, j, k, p, w0, w1, w2, a.ih[0], a.ih[1], a.ih[2]);
-    if (MODE == 4) {
-        // neighbours' first-sweep values damp * f_nb / D_nb
+    // neighbour offsets and couplings; a missing neighbour gets coupling 0
+    // and the point's own offset
+    constexpr int NN = 2 * DIM;
+    int off[NN];
+    cplx<T> cw[NN];
+    {
         const int64_t st[3] = {1, sy, sz};
         const int ci[3] = {i, j, k};
-        cplx<T> snb[3][2];
-        bool hasm[3], hasp[3];
 #pragma unroll
         for (int ax = 0; ax < DIM; ++ax) {
-            hasm[ax] = ci[ax] > 0;
-            hasp[ax] = ci[ax] + 1 < d.g[ax];
-            snb[ax][0] = hasm[ax] ? cdiv(mk<T>(damp, T(0)), D[p - st[ax]]) : czero<T>();
-            snb[ax][1] = hasp[ax] ? cdiv(mk<T>(damp, T(0)), D[p + st[ax]]) : czero<T>();
+            const bool hm = ci[ax] > 0, hp = ci[ax] + 1 < d.g[ax];
+            off[2 * ax] = hm ? -(int)st[ax] : 0;
+            off[2 * ax + 1] = hp ? (int)st[ax] : 0;
+            cw[2 * ax] = mk<T>(hm ? c.cm[ax] : T(0), T(0));
+            cw[2 * ax + 1] = mk<T>(hp ? c.cp[ax] : T(0), T(0));
+            if (MODE == 4) {
+                // fold the neighbour's first-sweep factor damp / D_nb in
+                cw[2 * ax] = cw[2 * ax] * (hm ? cdiv(mk<T>(damp, T(0)), D[p + off[2 * ax]]) : czero<T>());
+                cw[2 * ax + 1] = cw[2 * ax + 1] * (hp ? cdiv(mk<T>(damp, T(0)), D[p + off[2 * ax + 1]]) : czero<T>());
+            }
         }
-        const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
-        cplx<T>* out2 = a.out2[slot];
+    }
+    if (MODE == 4) {
+        cplx<T>* __restrict__ out2 = a.out2[slot];
         const int64_t vo2 = a.vo2[slot];
+#pragma unroll 2
         for (int r = 0; r < nrhs; ++r) {
-            const cplx<T>* fr = f + r * vf;
+            const cplx<T>* __restrict__ fr = f + r * vf;
             const cplx<T> fp = fr[p];
             const cplx<T> u0 = sc * fp;
             cplx<T> s = czero<T>();
 #pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) {
-                if (hasm[ax]) s = s + c.cm[ax] * (snb[ax][0] * fr[p - st[ax]]);
-                if (hasp[ax]) s = s + c.cp[ax] * (snb[ax][1] * fr[p + st[ax]]);
-            }
+            for (int t = 0; t < NN; ++t) s = s + cw[t] * fr[p + off[t]];
             out[r * vo + p] = u0;
             out2[r * vo2 + p] = fp - Dp * u0 + s;
         }
         return;
     }
-    const cplx<T>* u = a.u[slot];
+    const cplx<T>* __restrict__ u = a.u[slot];
     const int64_t vu = a.vu[slot];
+#pragma unroll 2
     for (int r = 0; r < nrhs; ++r) {
-        const cplx<T>* ur = u + r * vu;
+        const cplx<T>* __restrict__ ur = u + r * vu;
         const cplx<T> up = ur[p];
-        const cplx<T> off = c.offsum(d, i, j, k, p, ur);
+        cplx<T> offs = czero<T>();
+#pragma unroll
+        for (int t = 0; t < NN; ++t) offs = offs + cw[t] * ur[p + off[t]];
         if (MODE == 1) {
-            const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
-            out[r * vo + p] = up + sc * (f[r * vf + p] - Dp * up + off);
+            out[r * vo + p] = up + sc * (f[r * vf + p] - Dp * up + offs);
         } else if (MODE == 2) {
-            out[r * vo + p] = f[r * vf + p] - Dp * up + off;
+            out[r * vo + p] = f[r * vf + p] - Dp * up + offs;
         } else {
-            out[r * vo + p] = Dp * up - off;
+            out[r * vo + p] = Dp * up - offs;
         }
     }
 }
@@ -129,28 +140,75 @@ k_gfine(GArgs<T> a, int nrhs) {
 // ---------------------------------------------------------------------------
 // coarse levels (stored Galerkin stencils)
 
+// dinv = damping / centre coefficient, once per level at setup
+template <class T, int CENTRE>
+__global__ void k_dinv(int64_t np, const cplx<T>* __restrict__ coef, T damp, cplx<T>* __restrict__ dinv) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < np) dinv[p] = cdiv(mk<T>(damp, T(0)), coef[CENTRE * np + p]);
+}
+
 template <class T, int WX, int WY, int WZ, int MODE>
 __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const Dims& d, int i, int j, int k,
                                              int64_t p, int64_t sy, int64_t sz, int nrhs) {
     const int64_t np = d.np();
-    constexpr int NX = 2 * WX + 1, NY = 2 * WY + 1;
+    constexpr int NX = 2 * WX + 1, NY = 2 * WY + 1, NZ = 2 * WZ + 1;
+    constexpr int NST = NX * NY * NZ;
     constexpr int CENTRE = (WZ * NY + WY) * NX + WX;
-    const cplx<T>* coef = a.coef[slot];
-    const cplx<T>* f = a.f[slot];
-    cplx<T>* out = a.out[slot];
+    const cplx<T>* __restrict__ coef = a.coef[slot];
+    const cplx<T>* __restrict__ dinv = a.dinv[slot];
+    const cplx<T>* __restrict__ f = a.f[slot];
+    cplx<T>* __restrict__ out = a.out[slot];
     const int64_t vf = a.vf[slot], vo = a.vo[slot];
     const T damp = a.damp;
-    const cplx<T> Dp = coef[CENTRE * np + p];
-    const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
+    const cplx<T> sc = dinv[p];
     if (MODE == 0) {
         for (int r = 0; r < nrhs; ++r) out[r * vo + p] = sc * f[r * vf + p];
         return;
     }
-    const cplx<T>* u = a.u[slot];
+    const cplx<T>* __restrict__ u = a.u[slot];
     const int64_t vu = a.vu[slot];
+    if (NST <= 27) {
+        // stencil and neighbour offsets in registers; missing neighbours get a
+        // zero coefficient and the point's own offset, so the batch loop has
+        // no branches and every coefficient is read once per launch
+        cplx<T> cf[NST];
+        int off[NST];
+#pragma unroll
+        for (int oz = -WZ; oz <= WZ; ++oz)
+#pragma unroll
+            for (int oy = -WY; oy <= WY; ++oy)
+#pragma unroll
+                for (int ox = -WX; ox <= WX; ++ox) {
+                    const int o = ((oz + WZ) * NY + (oy + WY)) * NX + (ox + WX);
+                    const bool ok = (k + oz >= 0) && (k + oz < d.g[2]) && (j + oy >= 0) && (j + oy < d.g[1]) &&
+                                    (i + ox >= 0) && (i + ox < d.g[0]);
+                    off[o] = ok ? (int)(oz * sz + oy * sy + ox) : 0;
+                    cf[o] = ok ? coef[o * np + p] : czero<T>();
+                    if (MODE == 4) {
+                        // neighbour's first-sweep factor damp / D_nb folded into the coefficient
+                        cf[o] = cf[o] * (ok ? dinv[p + off[o]] : czero<T>());
+                    }
+                }
+#pragma unroll 2
+        for (int r = 0; r < nrhs; ++r) {
+            const cplx<T>* __restrict__ src = (MODE == 4) ? f + r * vf : u + r * vu;
+            cplx<T> xu = czero<T>();
+#pragma unroll
+            for (int o = 0; o < NST; ++o) xu = xu + cf[o] * src[p + off[o]];
+            const cplx<T> fp = f[r * vf + p];
+            if (MODE == 1) out[r * vo + p] = src[p] + sc * (fp - xu);
+            else if (MODE == 2) out[r * vo + p] = fp - xu;
+            else if (MODE == 3) out[r * vo + p] = xu;
+            else {
+                out[r * vo + p] = sc * fp;
+                a.out2[slot][r * a.vo2[slot] + p] = fp - xu;
+            }
+        }
+        return;
+    }
     for (int r = 0; r < nrhs; ++r) {
-        const cplx<T>* ur = u + r * vu;
-        const cplx<T>* fr = f + r * vf;
+        const cplx<T>* __restrict__ ur = u + r * vu;
+        const cplx<T>* __restrict__ fr = f + r * vf;
         cplx<T> xu = czero<T>();
 #pragma unroll
         for (int oz = -WZ; oz <= WZ; ++oz) {
@@ -164,7 +222,7 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
                     const int o = ((oz + WZ) * NY + (oy + WY)) * NX + (ox + WX);
                     const int64_t q = p + oz * sz + oy * sy + ox;
                     cplx<T> v;
-                    if (MODE == 4) v = cdiv(mk<T>(damp, T(0)), coef[CENTRE * np + q]) * fr[q];
+                    if (MODE == 4) v = dinv[q] * fr[q];
                     else v = ur[q];
                     xu = xu + coef[o * np + p] * v;
                 }
@@ -188,6 +246,10 @@ __global__ void __launch_bounds__(256)
 k_gstencil(GArgs<T> a, int nrhs) {
     EH_GROUP_POINT(a, d)
     const int kind = a.kind[slot];
+    if (a.mixed) {
+        stencil_body<T, 1, 1, (DIM == 3 ? 1 : 0), MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        return;
+    }
     if (DIM == 2) {
         if (kind == 0) stencil_body<T, 1, 2, 0, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
         else if (kind == 1) stencil_body<T, 2, 1, 0, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
@@ -205,16 +267,16 @@ k_gstencil(GArgs<T> a, int nrhs) {
 // writes out on the coarse grid) and prolongation (grid = fine level, adds P
 // of f (coarse) into out)
 
-template <class T, int DIM, int NM>
+template <class T, int DIM, int NM, bool MIXED>
 __device__ __forceinline__ void restrict_body(const GArgs<T>& a, int slot, const Dims& dc, int i, int j, int k,
                                               int64_t p, int nrhs) {
-    using RX = R1<(NM & 1) != 0>;
-    using RY = R1<(NM & 2) != 0>;
-    using RZ = R1<(NM & 4) != 0>;
+    using RX = R1<(NM & 1) != 0, MIXED>;
+    using RY = R1<(NM & 2) != 0, MIXED>;
+    using RZ = R1<(NM & 4) != 0, MIXED>;
     constexpr int SZ = DIM == 3 ? RZ::S : 1;
     const Dims df = a.dc[slot];      // for restriction dc[] holds the FINE grid
     const int64_t fsy = df.g[0], fsz = (int64_t)df.g[0] * df.g[1];
-    const int x0 = 2 * i - 1, y0 = 2 * j - 1, z0 = DIM == 3 ? 2 * k - 1 : 0;
+    const int x0 = 2 * i + RX::FIRST, y0 = 2 * j + RY::FIRST, z0 = DIM == 3 ? 2 * k + RZ::FIRST : 0;
     const cplx<T>* r = a.f[slot];
     cplx<T>* fc = a.out[slot];
     const int64_t vsf = a.vf[slot], vsc = a.vo[slot];
@@ -279,9 +341,11 @@ __global__ void __launch_bounds__(256)
 k_gtransfer(GArgs<T> a, int nrhs) {
     EH_GROUP_POINT(a, d)
     const int kind = a.kind[slot];
-#define EH_TB(NM)                                                      \
-    if (RESTRICT) restrict_body<T, DIM, NM>(a, slot, d, i, j, k, p, nrhs); \
-    else prolong_body<T, DIM, NM>(a, slot, d, i, j, k, p, nrhs);
+#define EH_TB(NM)                                                                       \
+    if (RESTRICT) {                                                                     \
+        if (a.mixed) restrict_body<T, DIM, NM, true>(a, slot, d, i, j, k, p, nrhs);     \
+        else restrict_body<T, DIM, NM, false>(a, slot, d, i, j, k, p, nrhs);            \
+    } else prolong_body<T, DIM, NM>(a, slot, d, i, j, k, p, nrhs);
     if (kind == DIM) { EH_TB(0) }
     else if (kind == 0) { EH_TB(1) }
     else if (kind == 1) { EH_TB(2) }

@@ -81,8 +81,13 @@ struct Transfer1D {
     int idx[4];
     float wt[4];
     int n;
-    __device__ __forceinline__ void restrict_support(int I, bool nodal, int nf) {
+    __device__ __forceinline__ void restrict_support(int I, bool nodal, int nf, bool mixed = false) {
         n = 0;
+        if (mixed && !nodal) {
+            // eq. tildeRu1: (1/2)[1 * 1], the two fine cells 2I and 2I+1
+            idx[0] = 2 * I; wt[0] = 0.5f; idx[1] = 2 * I + 1; wt[1] = 0.5f; n = 2;
+            return;
+        }
         if (nodal) {
             const int ks[3] = {2 * I - 1, 2 * I, 2 * I + 1};
             const float ws[3] = {0.25f, 0.5f, 0.25f};
@@ -112,11 +117,16 @@ struct Transfer1D {
 
 // Restriction and prolongation, specialised at compile time on the nodal
 // pattern NM of the block (bit a: nodal along axis a) and the dimension.
-template <bool NODAL>
+// 1D restriction along one axis: nodal (1/4)[1 2 1] from fine 2I-1;
+// cell-centred full weighting (1/8)[1 3 3 1] from fine 2I-1; cell-centred
+// mixed (eq. tildeRu1) (1/2)[1 1] from fine 2I.
+template <bool NODAL, bool MIXED = false>
 struct R1 {
-    static constexpr int S = NODAL ? 3 : 4;
+    static constexpr bool HALF = MIXED && !NODAL;
+    static constexpr int S = NODAL ? 3 : (HALF ? 2 : 4);
+    static constexpr int FIRST = HALF ? 0 : -1;       // first fine index is 2I + FIRST
     __device__ static constexpr float w(int t) {
-        return NODAL ? (t == 1 ? 0.5f : 0.25f) : ((t == 1 || t == 2) ? 0.375f : 0.125f);
+        return NODAL ? (t == 1 ? 0.5f : 0.25f) : (HALF ? 0.5f : ((t == 1 || t == 2) ? 0.375f : 0.125f));
     }
 };
 

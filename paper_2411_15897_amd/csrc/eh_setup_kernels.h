@@ -18,7 +18,7 @@ constexpr int GAL_MAXN = (2 * GAL_MAXW + 1) * (2 * GAL_MAXW + 1) * (2 * GAL_MAXW
 // coarse grid dc).  For coarse point I: sum over fine k in the support of
 // row I of R, over fine offsets o, over coarse parents J of l = k + o.
 __global__ void __launch_bounds__(64)
-k_galerkin(Dims df, Widths wf, const c128* __restrict__ cf, Dims dc, Widths wc, int nodal_mask,
+k_galerkin(Dims df, Widths wf, const c128* __restrict__ cf, Dims dc, Widths wc, int nodal_mask, int mixed,
            c128* __restrict__ cc, int* __restrict__ overflow) {
     const int64_t npc = dc.np();
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -32,9 +32,9 @@ k_galerkin(Dims df, Widths wf, const c128* __restrict__ cf, Dims dc, Widths wc, 
     const bool nz = (nodal_mask & 4) != 0;
     const bool three = (df.g[2] > 1) || nz;
     Transfer1D rx, ry, rz;
-    rx.restrict_support(I, nodal_mask & 1, df.g[0]);
-    ry.restrict_support(J, nodal_mask & 2, df.g[1]);
-    if (three) rz.restrict_support(K, nz, df.g[2]);
+    rx.restrict_support(I, nodal_mask & 1, df.g[0], mixed);
+    ry.restrict_support(J, nodal_mask & 2, df.g[1], mixed);
+    if (three) rz.restrict_support(K, nz, df.g[2], mixed);
     else { rz.n = 1; rz.idx[0] = 0; rz.wt[0] = 1.0f; }
     const int64_t npf = df.np();
     const int NXf = 2 * wf.w[0] + 1, NYf = 2 * wf.w[1] + 1;

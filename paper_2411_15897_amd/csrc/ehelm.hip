@@ -48,6 +48,7 @@ struct Level {
     Dims d{};
     Widths w{};              // stencil half widths (levels >= 1)
     void* coef = nullptr;    // levels >= 1: [nst][np] complex, multigrid precision
+    void* dinv = nullptr;    // levels >= 1: damping / diagonal, multigrid precision
     void* f = nullptr;       // right-hand side          (nrhs_cap * np)
     void* u = nullptr;       // iterate                  (nrhs_cap * np)
     void* t = nullptr;       // Jacobi ping-pong buffer  (nrhs_cap * np)
@@ -390,12 +391,12 @@ void build_hierarchy(eh_ctx* c, Block& B, const std::vector<c128>& st0) {
         Level& Lc = B.lev[l];
         const Level& Lf = B.lev[l - 1];
         Widths wc{{0, 0, 0}};
-        for (int a = 0; a < c->dim; ++a) wc.w[a] = (B.nodal_mask & (1 << a)) ? 1 : 2;
+        for (int a = 0; a < c->dim; ++a) wc.w[a] = (c->o.intergrid == 1 || (B.nodal_mask & (1 << a))) ? 1 : 2;
         Lc.w = wc;
         const int64_t npc = Lc.d.np();
         c128* cur = c->alloc<c128>((size_t)wc.nst() * npc);
         hipLaunchKernelGGL(k_galerkin, dim3(lin_grid(npc, 64, 1 << 30)), dim3(64), 0, 0, Lf.d, wprev,
-                           prev, Lc.d, wc, B.nodal_mask, cur, overflow);
+                           prev, Lc.d, wc, B.nodal_mask, c->o.intergrid, cur, overflow);
         HIPCHK(hipGetLastError());
         HIPCHK(hipDeviceSynchronize());
         // store in the multigrid precision
@@ -410,6 +411,29 @@ void build_hierarchy(eh_ctx* c, Block& B, const std::vector<c128>& st0) {
             HIPCHK(hipMemcpy(cf, cur, (size_t)wc.nst() * npc * sizeof(c128), hipMemcpyDeviceToDevice));
             Lc.coef = cf;
         }
+        {
+            // damping / centre coefficient of the stored stencil
+            const int ctr = (wc.w[2] * (2 * wc.w[1] + 1) + wc.w[1]) * (2 * wc.w[0] + 1) + wc.w[0];
+            const unsigned gl = (unsigned)((npc + 255) / 256);
+            if (f32) {
+                Lc.dinv = c->alloc<c64>(npc);
+#define EH_DI(CT) hipLaunchKernelGGL((k_dinv<float, CT>), dim3(gl), dim3(256), 0, 0, npc, (const c64*)Lc.coef, \
+                                     (float)Lc.damp, (c64*)Lc.dinv)
+                if (ctr == 7) EH_DI(7); else if (ctr == 12) EH_DI(12); else if (ctr == 37) EH_DI(37);
+                else if (ctr == 62) EH_DI(62); else if (ctr == 4) EH_DI(4); else if (ctr == 13) EH_DI(13);
+                else throw ArgError{"internal: unexpected stencil centre"};
+#undef EH_DI
+            } else {
+                Lc.dinv = c->alloc<c128>(npc);
+#define EH_DI(CT) hipLaunchKernelGGL((k_dinv<double, CT>), dim3(gl), dim3(256), 0, 0, npc, (const c128*)Lc.coef, \
+                                     Lc.damp, (c128*)Lc.dinv)
+                if (ctr == 7) EH_DI(7); else if (ctr == 12) EH_DI(12); else if (ctr == 37) EH_DI(37);
+                else if (ctr == 62) EH_DI(62); else if (ctr == 4) EH_DI(4); else if (ctr == 13) EH_DI(13);
+                else throw ArgError{"internal: unexpected stencil centre"};
+#undef EH_DI
+            }
+            HIPCHK(hipGetLastError());
+        }
         HIPCHK(hipDeviceSynchronize());
         c->release(prev);
         prev = cur;
@@ -422,7 +446,8 @@ void build_hierarchy(eh_ctx* c, Block& B, const std::vector<c128>& st0) {
     // coarsest: dense inverse by Gauss-Jordan with partial pivoting (FP64)
     const Level& Lc = B.lev[L - 1];
     const int64_t N = Lc.d.np();
-    if (N > 20000) throw ArgError{"coarsest grid too large for the dense direct solve (use more levels)"};
+    // the dense inverse costs 16 N^2 bytes and O(N^3) setup: keep N modest
+    if (N > 6000) throw ArgError{"coarsest grid too large for the dense direct solve (use more levels)"};
     c128* M = c->alloc<c128>((size_t)N * 2 * N);
     hipLaunchKernelGGL(k_dense_from_stencil, dim3(lin_grid(N, 64, 1 << 30)), dim3(64), 0, 0, Lc.d, wprev, prev, M);
     HIPCHK(hipGetLastError());
@@ -491,10 +516,12 @@ GArgs<T> gbase(eh_ctx* c, const int* kinds, int ns, int l, bool coarse_dims_for_
             a.D[s] = (const cplx<T>*)B.fD;
         } else {
             a.coef[s] = (const cplx<T>*)B.lev[l].coef;
+            a.dinv[s] = (const cplx<T>*)B.lev[l].dinv;
         }
     }
     a.damp = T(c->blk[kinds[0]].lev[l].damp);
     for (int ax = 0; ax < 3; ++ax) a.ih[ax] = T(1.0 / (c->h[ax] * c->h[ax]));
+    a.mixed = c->o.intergrid == 1;
     return a;
 }
 
@@ -1141,6 +1168,7 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
     if (o.mg_precision != 32 && o.mg_precision != 64) { g_create_error = "mg_precision must be 32 or 64"; return EH_ERR_ARG; }
     if (o.restart < 1 || o.restart > KRY_MAXM) { g_create_error = "restart must be in [1, 32]"; return EH_ERR_ARG; }
     if (o.abc_width < 0) { g_create_error = "abc_width must be >= 0"; return EH_ERR_ARG; }
+    if (o.intergrid != 0 && o.intergrid != 1) { g_create_error = "intergrid must be 0 (full) or 1 (mixed)"; return EH_ERR_ARG; }
     if (!(o.alpha >= 0.0) || !std::isfinite(o.alpha)) { g_create_error = "alpha must be >= 0"; return EH_ERR_ARG; }
     int64_t ncell = 1;
     for (int a = 0; a < dim; ++a) {

@@ -239,3 +239,53 @@ def test_operator_parity_full_size_1024():
     y = gpu.apply_operator(to_dev(x)).cpu().numpy()
     assert rel(y, s.apply_H(x)) <= 1e-12
     gpu.close()
+
+
+@pytest.mark.parametrize("n,levels", [((16, 16), 3), ((8, 8, 8), 3)])
+def test_mixed_intergrid_levels_and_cycle_fp64(n, levels):
+    """Mixed intergrid (eq. tildeRu1): Galerkin levels and one cycle per
+    block against the oracle, 2D and 3D, V(2,2) with the 3D damping."""
+    say("mixed intergrid parity", n, levels)
+    alpha, nu, damping = 0.3, (2, 2), (0.8, 0.8, 0.2)
+    gpu, s = make(n, seed=12, levels=levels, alpha=alpha, mg_precision=64, nu=nu,
+                  damping=damping, intergrid="mixed")
+    d = s.dim
+    for b in range(d + 1):
+        X = s.H_p(alpha) if b == d else s.A_block(b, alpha)
+        nodal = tuple(False for _ in range(d)) if b == d else face_nodal(d, b)
+        mg = Hierarchy(X, s.n, nodal, levels, damping=damping, nu=nu, intergrid="mixed")
+        for l in range(levels):
+            x = crand(mg.ops[l].shape[0], 30 + l)
+            y = gpu.block_apply(b, l, to_dev(x)).cpu().numpy()
+            assert rel(y, mg.ops[l] @ x) <= 1e-12, (b, l)
+        f = crand(X.shape[0], 40 + b)
+        e = gpu.block_cycle(b, to_dev(f)).cpu().numpy()
+        assert rel(e, mg(f)) <= 1e-10, b
+    gpu.close()
+
+
+def test_solve_3d_layered_small():
+    """The 3D layered-with-inclusion workload at 24^3 (4 sources, mixed
+    intergrid, V(2,2), complex64 multigrid): true residual below 1e-6 as
+    recomputed by the oracle, iteration count within 2 of the oracle's
+    FP64 FGMRES with the same preconditioner settings."""
+    say("3D solve 24^3")
+    from paper_2411_15897_amd import ElasticHelmholtz
+    wl = W.config(5, scale=8)
+    kw = dict(levels=3, nu=wl.nu, damping=wl.damping, alpha=wl.alpha, restart=wl.restart,
+              abc_width=wl.abc_width, abc_sides=wl.abc_sides, intergrid=wl.intergrid)
+    gpu = ElasticHelmholtz(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, mg_precision=32, **kw)
+    b = W.point_source_rhs(wl.n, wl.h, wl.sources)
+    x, info = gpu.solve(to_dev(b), tol=1e-6, maxit=500)
+    s = ElasticSystem(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, wl.abc_width, wl.abc_sides)
+    H = s.H()
+    xs = x.cpu().numpy()
+    M = BlockAcoustic(s, alpha=wl.alpha, solver="mg", levels=3, cycle="V", nu=wl.nu,
+                      damping=wl.damping, intergrid="mixed")
+    ref = fgmres(lambda v: H @ v, M, b[0], restart=wl.restart, tol=1e-6, maxit=500)
+    for k in range(b.shape[0]):
+        rr = np.linalg.norm(b[k] - H @ xs[k]) / np.linalg.norm(b[k])
+        assert info[k]["converged"] and rr < 1e-6
+    say(f"  gpu iters {[i['iters'] for i in info]} oracle iters (source 0) {ref.iters}")
+    assert abs(info[0]["iters"] - ref.iters) <= 2
+    gpu.close()

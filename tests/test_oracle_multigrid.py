@@ -124,3 +124,45 @@ def test_galerkin_operator_is_symmetric_for_Ak():
     mg = Hierarchy(s.A_block(1, 0.3), n, face_nodal(2, 1), levels=3)
     for op in mg.ops:
         assert abs(op - op.T).max() <= 1e-12 * abs(op).max()
+
+
+def test_mixed_restriction_stencils_match_paper():
+    """eq. tildeRu1: R~_u1 = 1/4[1 2 1] (x) 1/2[1 * 1] (6 nonzeros per row),
+    R~_p = 1/2[1 * 1] (x) 1/2[1 * 1] (4 nonzeros)."""
+    g = json.load(open(GOLD))
+    n = (8, 8)
+    _, R = transfer(n, (True, False), "mixed")
+    nxc = n[0] // 2 + 1
+    I, J = 2, 2
+    row = R.getrow(J * nxc + I).toarray().reshape(n[1], n[0] + 1)
+    expect = np.zeros_like(row)
+    for a, wy in enumerate(g["mixed_cell_centred"]):
+        for b, wx in enumerate(g["nodal"]):
+            expect[2 * J + a, 2 * I - 1 + b] = wy * wx
+    np.testing.assert_allclose(row, expect, atol=1e-15)
+    assert row.astype(bool).sum() == g["nnz_Rt_u"]
+    _, Rp = transfer(n, (False, False), "mixed")
+    row = Rp.getrow(J * (n[0] // 2) + I).toarray().reshape(n[1], n[0])
+    assert row.astype(bool).sum() == g["nnz_Rt_p"]
+    np.testing.assert_allclose(row[2 * J:2 * J + 2, 2 * I:2 * I + 2], 0.25)
+
+
+@pytest.mark.parametrize("which", ["u1", "p"])
+def test_mixed_galerkin_projection_and_27_point_stencil(which):
+    """With R~ the coarse-grid correction is still a projection
+    ((I - P X_c^-1 R~ X) P = 0), and the 3D Galerkin operators stay 27-point
+    (3 wide per axis) on every level."""
+    n = (8, 8, 8)
+    s = _block(n, 0.3)
+    if which == "u1":
+        X, nodal = s.A_block(0, 0.3), face_nodal(3, 0)
+    else:
+        X, nodal = s.H_p(0.3), (False, False, False)
+    P, R = transfer(n, nodal, "mixed")
+    Xc = (R @ X @ P).toarray()
+    Pd, Rd, Xd = P.toarray(), R.toarray(), X.toarray()
+    E = Pd - Pd @ np.linalg.solve(Xc, Rd @ Xd @ Pd)
+    assert np.abs(E).max() <= 1e-11 * np.abs(Pd).max()
+    mg = Hierarchy(X, n, nodal, 3, intergrid="mixed")
+    for op in mg.ops[1:]:
+        assert np.diff(op.tocsr().indptr).max() <= 27

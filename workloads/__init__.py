@@ -70,6 +70,7 @@ class Workload:
     restart: int = 20
     tol: float = 1e-6
     gamma0: float = 0.01 * math.pi
+    intergrid: str = "full"        # "mixed": eq. tildeRu1 restriction (3D setting)
 
     @property
     def dim(self) -> int:
@@ -199,7 +200,7 @@ def config(k: int, scale: int = 1) -> Workload:
         src = [(1, (n[0] // 2, 1))]
         return Workload("config2_layered_1024", n, h, vp, vs, rho, omega,
                         abc_width=20, abc_sides=abc_all_but_top(2),
-                        sources=src, levels=5, alpha=0.3, restart=20)
+                        sources=src, levels=6, alpha=0.6, restart=10)
     if k == 3:
         n = (512 // scale, 512 // scale)
         vp, vs, rho = layered_medium(n, seed=1)
@@ -219,7 +220,7 @@ def config(k: int, scale: int = 1) -> Workload:
         src = [(1, ((32 + 64 * s) // scale, 1)) for s in range(32)]
         return Workload("config4_layered_2048_b32", n, h, vp, vs, rho, omega,
                         abc_width=20, abc_sides=abc_all_but_top(2),
-                        sources=src, levels=6, alpha=0.3, restart=20)
+                        sources=src, levels=7, alpha=0.7, restart=10)
     if k == 5:
         n = (192 // scale,) * 3
         vp, vs, rho = layered_inclusion_medium_3d(n, seed=4)
@@ -229,9 +230,10 @@ def config(k: int, scale: int = 1) -> Workload:
         src = [(2, (m // 3, m // 3, 1)), (2, (2 * m // 3, m // 3, 1)),
                (2, (m // 3, 2 * m // 3, 1)), (2, (2 * m // 3, 2 * m // 3, 1))]
         return Workload("config5_layered_192cube", n, h, vp, vs, rho, omega,
-                        abc_width=12, abc_sides=abc_all_but_top(3),
-                        sources=src, levels=4, nu=(2, 2),
-                        damping=(0.8, 0.8, 0.2), alpha=0.3, restart=20)
+                        abc_width=max(12 // scale, 1), abc_sides=abc_all_but_top(3),
+                        sources=src, levels=5, nu=(2, 2),
+                        damping=(0.8, 0.8, 0.2), alpha=0.8, restart=10,
+                        intergrid="mixed")
     raise ValueError(f"unknown config {k}")
 
 
