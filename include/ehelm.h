@@ -28,6 +28,8 @@
  *    `const double *` medium arrays are HOST pointers, copied during create.
  *  - All work is enqueued on the context's HIP stream.  Calls return after
  *    enqueue, except eh_create, eh_solve and eh_gradient which synchronise.
+ *    eh_solve runs on a stream of its own, ordered after the context's
+ *    stream, and returns when its work is complete.
  *  - Errors are returned as status codes; nothing throws across this
  *    boundary and nothing exits.  eh_last_error gives a message.  Argument
  *    errors are detected before any device work and leave no side effects.
@@ -68,6 +70,9 @@ typedef struct {
     int intergrid;          /* 0: full-weighting restriction R = P^T/2^d (eqs. Ru1, Rp);
                                1: mixed intergrid, (1/2)[1 * 1] along cell-centred axes
                                (eq. tildeRu1, the paper's 3D setting); P is (bi/tri)linear either way */
+    int graphs;             /* 1: eh_solve captures each Arnoldi step (preconditioner, operator, first
+                               Gram-Schmidt pass) as a HIP graph once and replays it; 0: plain launches.
+                               While a kernel class is timed (eh_timer_enable) plain launches are used. */
 } eh_opts;
 
 typedef struct {

@@ -36,7 +36,7 @@ class EhOpts(ctypes.Structure):
         ("alpha", ctypes.c_double), ("mg_precision", ctypes.c_int),
         ("restart", ctypes.c_int), ("abc_width", ctypes.c_int),
         ("abc_sides", ctypes.c_uint), ("gamma0", ctypes.c_double),
-        ("intergrid", ctypes.c_int),
+        ("intergrid", ctypes.c_int), ("graphs", ctypes.c_int),
     ]
 
 

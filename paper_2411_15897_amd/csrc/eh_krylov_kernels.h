@@ -160,6 +160,24 @@ k_scale(int64_t n, int nrhs, const double* __restrict__ s, const c128* __restric
         v[(int64_t)r * n + p] = sc * w[(int64_t)r * n + p];
 }
 
+// out = value (graph-safe fill)
+template <class V>
+__global__ void __launch_bounds__(256)
+k_fill(int64_t n, V* __restrict__ out, V value) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) out[p] = value;
+}
+
+// dst[r * vd + q] = src[r * vs + q] for q < n, r < nrhs (graph-safe copy)
+template <class V>
+__global__ void __launch_bounds__(256)
+k_copy_strided(int64_t n, int nrhs, const V* __restrict__ src, int64_t vs, V* __restrict__ dst, int64_t vd) {
+    const int r = blockIdx.y;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        dst[(int64_t)r * vd + q] = src[(int64_t)r * vs + q];
+}
+
 // out = a - b
 __global__ void __launch_bounds__(256)
 k_sub(int64_t n, const c128* __restrict__ a, const c128* __restrict__ b, c128* __restrict__ out) {

@@ -141,6 +141,13 @@ struct eh_ctx {
     struct TimerRec { int cls; hipEvent_t a, b; double bytes; };
     std::vector<TimerRec> timer_recs;
     std::vector<hipEvent_t> event_pool;
+    // captured Arnoldi steps: one graph per step j, valid for graph_nrhs
+    // right-hand sides; used only while no kernel class is being timed
+    struct GraphEntry { hipGraphExec_t exec = nullptr; hipGraph_t graph = nullptr; };
+    std::vector<GraphEntry> graphs;
+    int graph_nrhs = -1;
+    bool capturing = false;
+    hipStream_t solve_stream = nullptr;
 
     template <class P>
     P* alloc(size_t count) {
@@ -174,6 +181,15 @@ hipEvent_t take_event(eh_ctx* c) {
     return e;
 }
 
+void drop_graphs(eh_ctx* c) {
+    for (auto& g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+    c->graph_nrhs = -1;
+}
+
 // Records a start event before and a stop event after the launches in its
 // scope when the class is selected; `bytes` is the algorithmic traffic.
 struct Timed {
@@ -183,7 +199,8 @@ struct Timed {
     bool on;
     hipEvent_t a{}, b{};
     Timed(eh_ctx* c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
-        on = (c->timer_mask >> cls) & 1u;
+        // graphs are only captured with timing off, so events are plain
+        on = ((c->timer_mask >> cls) & 1u) && !c->capturing;
         if (on) {
             a = take_event(c);
             b = take_event(c);
@@ -477,6 +494,7 @@ void build_hierarchy(eh_ctx* c, Block& B, const std::vector<c128>& st0) {
 void ensure_mg_workspace(eh_ctx* c, int nrhs) {
     if (nrhs <= c->nrhs_cap) return;
     HIPCHK(hipStreamSynchronize(c->s));
+    drop_graphs(c);
     const size_t cs = c->csize();
     for (int b = 0; b < c->nblocks; ++b)
         for (auto& L : c->blk[b].lev) {
@@ -587,10 +605,11 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
 template <class T>
 void gcopy(eh_ctx* c, int ns, const void* const* src, const int64_t* vs, void* const* dst, const int64_t* vd,
            const int64_t* np, int nrhs) {
-    for (int s = 0; s < ns; ++s)
-        for (int r = 0; r < nrhs; ++r)
-            HIPCHK(hipMemcpyAsync((cplx<T>*)dst[s] + r * vd[s], (const cplx<T>*)src[s] + r * vs[s],
-                                  np[s] * sizeof(cplx<T>), hipMemcpyDeviceToDevice, c->s));
+    for (int s = 0; s < ns; ++s) {
+        hipLaunchKernelGGL((k_copy_strided<cplx<T>>), dim3(lin_grid(np[s], 256, 4096), nrhs), dim3(256), 0, c->s,
+                           np[s], nrhs, (const cplx<T>*)src[s], vs[s], (cplx<T>*)dst[s], vd[s]);
+        HIPCHK(hipGetLastError());
+    }
 }
 
 // One cycle on level l for X_l e = f, for the blocks kinds[0..ns).  f[s]
@@ -698,7 +717,9 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
         for (int t = 1; t < nu1; ++t) sweep(1, false);
     } else {
         for (int s = 0; s < ns; ++s) {
-            HIPCHK(hipMemsetAsync(L[s]->u, 0, (size_t)np[s] * nrhs * sizeof(cplx<T>), c->s));
+            hipLaunchKernelGGL((k_fill<cplx<T>>), dim3(lin_grid(np[s] * nrhs, 256, 4096)), dim3(256), 0, c->s,
+                               np[s] * nrhs, (cplx<T>*)L[s]->u, czero<T>());
+            HIPCHK(hipGetLastError());
             cur[s] = L[s]->u; vcur[s] = np[s];
         }
         nb = 1;
@@ -871,6 +892,7 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
 void ensure_krylov(eh_ctx* c, int nrhs, int m) {
     if (nrhs <= c->kry_nrhs && m <= c->kry_m) return;
     HIPCHK(hipStreamSynchronize(c->s));
+    drop_graphs(c);
     c->release(c->V); c->release(c->Z); c->release(c->W); c->release(c->partial);
     c->release(c->dsmall); c->release(c->dscale);
     c->V = c->alloc<c128>((size_t)(m + 1) * nrhs * c->ndof);
@@ -923,6 +945,7 @@ template <class T>
 eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, int maxit, eh_info* info) {
     const int m = c->o.restart;
     ensure_krylov(c, nrhs, m);
+    ensure_mg_workspace(c, nrhs);     // no allocation may happen inside a graph capture
     const int64_t n = c->ndof;
     const int64_t vstep = (int64_t)nrhs * n;    // distance between basis vectors
     cplx<T>* Z = (cplx<T>*)c->Z;
@@ -968,18 +991,49 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
         for (; j < m && total < maxit; ++j) {
             c128* Vj = c->V + (int64_t)j * vstep;
             cplx<T>* Zj = Z + (int64_t)j * vstep;
-            apply_M<T>(c, Vj, n, Zj, n, nrhs);
-            apply_H<T>(c, Zj, n, c->W, n, nrhs);
+            c128* d1 = c->dsmall;
+            c128* d2 = c->dsmall + (size_t)2 * nrhs * (m + 2);
+            c128* d3 = c->dsmall + (size_t)4 * nrhs * (m + 2);
+            // One Arnoldi step on the device: z_j = M v_j, w = H z_j, and the
+            // first Gram-Schmidt pass (h1 = V^H w and the Gram column V^H v_j).
+            auto body = [&]() {
+                apply_M<T>(c, Vj, n, Zj, n, nrhs);
+                apply_H<T>(c, Zj, n, c->W, n, nrhs);
+                gs_pass<4>(c, j + 1, nrhs, c->V, c->W, nullptr, d1);
+            };
+            if (c->o.graphs && c->timer_mask == 0) {
+                if (c->graph_nrhs != nrhs || (int)c->graphs.size() != m) {
+                    drop_graphs(c);
+                    c->graphs.resize(m);
+                    c->graph_nrhs = nrhs;
+                }
+                eh_ctx::GraphEntry& g = c->graphs[j];
+                if (!g.exec) {
+                    HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeRelaxed));
+                    c->capturing = true;
+                    try {
+                        body();
+                    } catch (...) {
+                        c->capturing = false;
+                        hipGraph_t tmp = nullptr;
+                        (void)hipStreamEndCapture(c->s, &tmp);
+                        if (tmp) (void)hipGraphDestroy(tmp);
+                        throw;
+                    }
+                    c->capturing = false;
+                    HIPCHK(hipStreamEndCapture(c->s, &g.graph));
+                    HIPCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+                }
+                HIPCHK(hipGraphLaunch(g.exec, c->s));
+            } else {
+                body();
+            }
             ++total;
             // Classical Gram-Schmidt with one reorthogonalisation (CGS2) in two
             // passes: the first gives h1 = V^H w and the newest Gram column
             // V^H v_j; the second-pass coefficients follow exactly from
             // h2 = V^H (w - V h1) = h1 - G h1 with G = V^H V, so the update
             // w <- w - V (h1 + h2) and ||w|| take one more pass.
-            c128* d1 = c->dsmall;
-            c128* d2 = c->dsmall + (size_t)2 * nrhs * (m + 2);
-            c128* d3 = c->dsmall + (size_t)4 * nrhs * (m + 2);
-            gs_pass<4>(c, j + 1, nrhs, c->V, c->W, nullptr, d1);
             HIPCHK(hipMemcpyAsync(h1.data(), d1, (size_t)nrhs * 2 * (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, c->s));
             HIPCHK(hipStreamSynchronize(c->s));
             for (int r = 0; r < nrhs; ++r) {
@@ -1104,6 +1158,8 @@ eh_status from_hip(eh_ctx* c, const HipError& e) {
 }
 
 void destroy_all(eh_ctx* c) {
+    drop_graphs(c);
+    if (c->solve_stream) { (void)hipStreamDestroy(c->solve_stream); c->solve_stream = nullptr; }
     for (auto& r : c->timer_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     c->timer_recs.clear();
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
@@ -1136,6 +1192,8 @@ void eh_default_opts(eh_opts* o) {
     o->abc_width = 20;
     o->abc_sides = 0;   // filled per dim in eh_create when zero: all but the top
     o->gamma0 = 0.01 * M_PI;
+    o->intergrid = 0;
+    o->graphs = 1;
 }
 
 const char* eh_last_error(const eh_ctx* c) {
@@ -1169,6 +1227,7 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
     if (o.restart < 1 || o.restart > KRY_MAXM) { g_create_error = "restart must be in [1, 32]"; return EH_ERR_ARG; }
     if (o.abc_width < 0) { g_create_error = "abc_width must be >= 0"; return EH_ERR_ARG; }
     if (o.intergrid != 0 && o.intergrid != 1) { g_create_error = "intergrid must be 0 (full) or 1 (mixed)"; return EH_ERR_ARG; }
+    if (o.graphs != 0 && o.graphs != 1) { g_create_error = "graphs must be 0 or 1"; return EH_ERR_ARG; }
     if (!(o.alpha >= 0.0) || !std::isfinite(o.alpha)) { g_create_error = "alpha must be >= 0"; return EH_ERR_ARG; }
     int64_t ncell = 1;
     for (int a = 0; a < dim; ++a) {
@@ -1452,12 +1511,27 @@ eh_status eh_block_apply(eh_ctx* c, int block, int level, const void* x, void* y
 eh_status eh_solve(eh_ctx* c, const void* b, void* x, int nrhs, double tol, int maxit, eh_info* info) {
     EH_GUARD(c)
     if (!b || !x || nrhs < 1 || !(tol > 0.0) || maxit < 0) return fail(c, EH_ERR_ARG, "invalid solve arguments");
+    hipStream_t user = c->s;
     try {
+        // the solve runs on the context's own stream (graphs cannot be
+        // captured on the legacy default stream), ordered after the user's
+        // stream by an event; the host waits for it before returning
+        if (!c->solve_stream) HIPCHK(hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking));
+        hipEvent_t ev = take_event(c);
+        HIPCHK(hipEventRecord(ev, user));
+        HIPCHK(hipStreamWaitEvent(c->solve_stream, ev, 0));
+        c->event_pool.push_back(ev);
+        c->s = c->solve_stream;
         eh_status st;
         if (c->o.mg_precision == 64) st = solve_impl<double>(c, (const c128*)b, (c128*)x, nrhs, tol, maxit, info);
         else st = solve_impl<float>(c, (const c128*)b, (c128*)x, nrhs, tol, maxit, info);
+        HIPCHK(hipStreamSynchronize(c->s));
+        c->s = user;
         return st;
-    } catch (const HipError& e) { return from_hip(c, e); }
+    } catch (const HipError& e) {
+        c->s = user;
+        return from_hip(c, e);
+    }
 }
 
 }  // extern "C"

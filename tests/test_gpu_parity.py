@@ -289,3 +289,33 @@ def test_solve_3d_layered_small():
     say(f"  gpu iters {[i['iters'] for i in info]} oracle iters (source 0) {ref.iters}")
     assert abs(info[0]["iters"] - ref.iters) <= 2
     gpu.close()
+
+
+def test_graph_replay_equals_eager():
+    """eh_solve with captured Arnoldi-step graphs (replayed many times, with
+    the host's eager work and synchronisations between replays) gives
+    bitwise the same iterates as plain launches (timing a kernel class
+    switches to plain launches); repeated solves replay the same graphs."""
+    say("graph replay vs eager")
+    n = (64, 48)
+    res = []
+    for graphs, timers in ((True, False), (True, False), (False, False), (True, True)):
+        gpu, s = make(n, seed=13, levels=4, alpha=0.4, mg_precision=32, restart=8, graphs=graphs)
+        if timers:
+            gpu.timer_enable(["coarse", "fine_sweep"])
+        b = np.zeros((2, s.ndof), dtype=np.complex128)
+        b[0, s.face_sizes[0] + 100] = -1.0
+        b[1] = crand(s.ndof, 14)
+        bt = to_dev(b)
+        x1, i1 = gpu.solve(bt, tol=1e-8, maxit=400)
+        x2, i2 = gpu.solve(bt, tol=1e-8, maxit=400)     # second solve replays the graphs
+        assert torch.equal(x1, x2)
+        assert [i["iters"] for i in i1] == [i["iters"] for i in i2]
+        if timers:
+            nl, ms, by = gpu.timer_read("coarse")
+            assert nl > 0 and ms > 0 and by > 0
+        res.append((x1.cpu().numpy(), [i["iters"] for i in i1]))
+        gpu.close()
+    for x, its in res[1:]:
+        assert its == res[0][1]
+        assert np.array_equal(x, res[0][0])
