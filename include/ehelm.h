@@ -73,6 +73,10 @@ typedef struct {
     int graphs;             /* 1: eh_solve captures each Arnoldi step (preconditioner, operator, first
                                Gram-Schmidt pass) as a HIP graph once and replays it; 0: plain launches.
                                While a kernel class is timed (eh_timer_enable) plain launches are used. */
+    int autotune;           /* 1: at the first solve / preconditioner call for a batch size, time every
+                               candidate workgroup shape of the sweep, restriction and prolongation kernels
+                               per level and block group and keep the fastest (results are unchanged);
+                               choices are cached in the file named by $EH_TUNE_CACHE when set */
 } eh_opts;
 
 typedef struct {

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -71,6 +72,12 @@ dim3 grid_of(const Dims& d) {
     return dim3((unsigned)((d.g[0] + 63) / 64), (unsigned)((d.g[1] + 3) / 4), (unsigned)d.g[2]);
 }
 const dim3 kBlock(64, 4, 1);
+
+// Workgroup shapes the autotuner chooses from (all 256 threads or fewer,
+// the kernels' launch bound); shape 0 is the default.
+const int kShapes[][2] = {{64, 4}, {32, 8}, {128, 2}, {256, 1}, {16, 16}, {64, 2}, {32, 4}};
+constexpr int kNumShapes = 7;
+constexpr int kMaxLevels = 12;
 
 unsigned lin_grid(int64_t n, int threads = 256, int64_t cap = 65535) {
     int64_t g = (n + threads - 1) / threads;
@@ -148,6 +155,10 @@ struct eh_ctx {
     int graph_nrhs = -1;
     bool capturing = false;
     hipStream_t solve_stream = nullptr;
+    // launch shapes per block group (0: H_p, 1: shear blocks), level and
+    // kernel kind (0: sweeps/residuals, 1: restriction, 2: prolongation)
+    int shape[2][kMaxLevels][3] = {};
+    int tuned_nrhs = 0;
 
     template <class P>
     P* alloc(size_t count) {
@@ -544,13 +555,21 @@ GArgs<T> gbase(eh_ctx* c, const int* kinds, int ns, int l, bool coarse_dims_for_
 }
 
 template <class T>
-dim3 ggrid(const GArgs<T>& a) {
+dim3 ggrid(const GArgs<T>& a, const dim3& blk) {
     int gx = 1, gy = 1;
     for (int s = 0; s < a.ns; ++s) {
-        gx = std::max(gx, (a.d[s].g[0] + 63) / 64);
-        gy = std::max(gy, (a.d[s].g[1] + 3) / 4);
+        gx = std::max(gx, (int)((a.d[s].g[0] + blk.x - 1) / blk.x));
+        gy = std::max(gy, (int)((a.d[s].g[1] + blk.y - 1) / blk.y));
     }
     return dim3((unsigned)gx, (unsigned)gy, (unsigned)(a.maxg2 * a.ns));
+}
+
+// block group of a launch: 0 for H_p, 1 for the shear blocks
+inline int group_of(const eh_ctx* c, int kind0) { return kind0 == c->dim ? 0 : 1; }
+
+inline dim3 shape_block(const eh_ctx* c, int group, int l, int which) {
+    const int* sh = kShapes[c->shape[group][std::min(l, kMaxLevels - 1)][which]];
+    return dim3((unsigned)sh[0], (unsigned)sh[1], 1);
 }
 
 // One sweep-type launch (modes of k_gfine / k_gstencil) on level l.
@@ -570,9 +589,10 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
     const int cls = l > 0 ? KC_COARSE
                           : (mode == 0 || mode == 4 ? KC_FINE_FIRST : (mode == 1 ? KC_FINE_SWEEP : KC_FINE_RESID));
     Timed tm(c, cls, by);
-    const dim3 g = ggrid(a);
+    const dim3 blk = shape_block(c, group_of(c, kind0), l, 0);
+    const dim3 g = ggrid(a, blk);
     if (l == 0) {
-#define EH_GF(KIND, DIM, MODE) hipLaunchKernelGGL((k_gfine<T, KIND, DIM, MODE>), g, kBlock, 0, c->s, a, nrhs)
+#define EH_GF(KIND, DIM, MODE) hipLaunchKernelGGL((k_gfine<T, KIND, DIM, MODE>), g, blk, 0, c->s, a, nrhs)
 #define EH_GF_M(KIND, DIM)                      \
     switch (mode) {                             \
         case 0: EH_GF(KIND, DIM, 0); break;     \
@@ -586,7 +606,7 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
 #undef EH_GF_M
 #undef EH_GF
     } else {
-#define EH_GS(DIM, MODE) hipLaunchKernelGGL((k_gstencil<T, DIM, MODE>), g, kBlock, 0, c->s, a, nrhs)
+#define EH_GS(DIM, MODE) hipLaunchKernelGGL((k_gstencil<T, DIM, MODE>), g, blk, 0, c->s, a, nrhs)
 #define EH_GS_M(DIM)                        \
     switch (mode) {                         \
         case 0: EH_GS(DIM, 0); break;       \
@@ -756,8 +776,9 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
             by += (double)(np[s] + npc[s]) * nrhs * sizeof(cplx<T>);
         }
         Timed tm(c, KC_RESTRICT, by);
-        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, true>), ggrid(t), kBlock, 0, c->s, t, nrhs);
-        else hipLaunchKernelGGL((k_gtransfer<T, 3, true>), ggrid(t), kBlock, 0, c->s, t, nrhs);
+        const dim3 blk = shape_block(c, group_of(c, kinds[0]), l, 1);
+        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, true>), ggrid(t, blk), blk, 0, c->s, t, nrhs);
+        else hipLaunchKernelGGL((k_gtransfer<T, 3, true>), ggrid(t, blk), blk, 0, c->s, t, nrhs);
         HIPCHK(hipGetLastError());
     }
     const int ncalls = (c->o.cycle == 1) ? 2 : 1;
@@ -774,14 +795,170 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
             by += (double)(2 * np[s] + npc[s]) * nrhs * sizeof(cplx<T>);
         }
         Timed tm(c, KC_PROLONG, by);
-        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, false>), ggrid(t), kBlock, 0, c->s, t, nrhs);
-        else hipLaunchKernelGGL((k_gtransfer<T, 3, false>), ggrid(t), kBlock, 0, c->s, t, nrhs);
+        const dim3 blk = shape_block(c, group_of(c, kinds[0]), l, 2);
+        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, false>), ggrid(t, blk), blk, 0, c->s, t, nrhs);
+        else hipLaunchKernelGGL((k_gtransfer<T, 3, false>), ggrid(t, blk), blk, 0, c->s, t, nrhs);
         HIPCHK(hipGetLastError());
     }
     for (int t = 0; t < nu2; ++t) sweep(1, t == nu2 - 1);
     bool need_copy = false;
     for (int s = 0; s < ns; ++s) if (cur[s] != out[s]) need_copy = true;
     if (need_copy) gcopy<T>(c, ns, cur, vcur, out, vo, np, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape autotuner
+
+std::string tune_signature(const eh_ctx* c, int nrhs) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "d%d n%lldx%lldx%lld L%d p%d i%d r%d", c->dim, (long long)c->n[0],
+                  (long long)c->n[1], (long long)c->n[2], c->o.levels, c->o.mg_precision, c->o.intergrid, nrhs);
+    return buf;
+}
+
+bool tune_cache_load(eh_ctx* c, const std::string& sig) {
+    const char* path = std::getenv("EH_TUNE_CACHE");
+    if (!path) return false;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return false;
+    char line[4096];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), fp)) {
+        std::string ln(line);
+        const size_t bar = ln.find(" | ");
+        if (bar == std::string::npos || ln.substr(0, bar) != sig) continue;
+        const char* q = ln.c_str() + bar + 3;
+        int vals[2 * kMaxLevels * 3];
+        int cnt = 0;
+        char* end = nullptr;
+        while (cnt < 2 * kMaxLevels * 3) {
+            long v = std::strtol(q, &end, 10);
+            if (end == q) break;
+            vals[cnt++] = (int)v;
+            q = end;
+        }
+        const int need = 2 * c->o.levels * 3;
+        if (cnt != need) continue;
+        bool ok = true;
+        for (int t = 0; t < cnt; ++t) if (vals[t] < 0 || vals[t] >= kNumShapes) ok = false;
+        if (!ok) continue;
+        int t = 0;
+        for (int g = 0; g < 2; ++g)
+            for (int l = 0; l < c->o.levels; ++l)
+                for (int w = 0; w < 3; ++w) c->shape[g][l][w] = vals[t++];
+        found = true;
+    }
+    std::fclose(fp);
+    return found;
+}
+
+void tune_cache_store(const eh_ctx* c, const std::string& sig) {
+    const char* path = std::getenv("EH_TUNE_CACHE");
+    if (!path) return;
+    FILE* fp = std::fopen(path, "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s |", sig.c_str());
+    for (int g = 0; g < 2; ++g)
+        for (int l = 0; l < c->o.levels; ++l)
+            for (int w = 0; w < 3; ++w) std::fprintf(fp, " %d", c->shape[g][l][w]);
+    std::fprintf(fp, "\n");
+    std::fclose(fp);
+}
+
+// Time `launch` (one launch per call) for every shape; return the fastest.
+template <class F>
+int pick_shape(eh_ctx* c, F launch) {
+    hipEvent_t a = take_event(c), b = take_event(c);
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+        const dim3 blk((unsigned)kShapes[sh][0], (unsigned)kShapes[sh][1], 1);
+        launch(blk);                                   // warm-up
+        HIPCHK(hipEventRecord(a, c->s));
+        for (int rep = 0; rep < 3; ++rep) launch(blk);
+        HIPCHK(hipEventRecord(b, c->s));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        if (ms < best_ms) { best_ms = ms; best = sh; }
+    }
+    c->event_pool.push_back(a);
+    c->event_pool.push_back(b);
+    return best;
+}
+
+// Pick the workgroup shape of the sweep, restriction and prolongation
+// kernels of every level and block group for this batch size, timing each
+// candidate on the level's own buffers.  Arithmetic per point does not
+// depend on the shape, so results are unchanged bitwise.
+template <class T>
+void maybe_autotune(eh_ctx* c, int nrhs) {
+    if (!c->o.autotune || c->tuned_nrhs == nrhs) return;
+    ensure_mg_workspace(c, nrhs);
+    drop_graphs(c);
+    const std::string sig = tune_signature(c, nrhs);
+    if (tune_cache_load(c, sig)) { c->tuned_nrhs = nrhs; return; }
+    const unsigned saved_mask = c->timer_mask;
+    c->timer_mask = 0;
+    const int L = c->o.levels;
+    for (int g = 0; g < 2; ++g) {
+        int kinds[GMAX];
+        int ns = 0;
+        if (g == 0) kinds[ns++] = c->dim;
+        else for (int k = 0; k < c->dim; ++k) kinds[ns++] = k;
+        for (int l = 0; l < L; ++l) {
+            for (int s = 0; s < ns; ++s) {
+                Level& Lv = c->blk[kinds[s]].lev[l];
+                const int64_t tot = Lv.d.np() * nrhs;
+                for (void* p : {Lv.f, Lv.u, Lv.t, Lv.r, Lv.e})
+                    hipLaunchKernelGGL((k_fill<cplx<T>>), dim3(lin_grid(tot, 256, 4096)), dim3(256), 0, c->s, tot,
+                                       (cplx<T>*)p, mk<T>(T(0.5), T(-0.25)));
+            }
+            HIPCHK(hipGetLastError());
+            if (l == L - 1) break;
+            // sweeps
+            GArgs<T> a = gbase<T>(c, kinds, ns, l, false);
+            for (int s = 0; s < ns; ++s) {
+                Level& Lv = c->blk[kinds[s]].lev[l];
+                a.f[s] = (const cplx<T>*)Lv.f; a.vf[s] = Lv.d.np();
+                a.u[s] = (const cplx<T>*)Lv.u; a.vu[s] = Lv.d.np();
+                a.out[s] = (cplx<T>*)Lv.t; a.vo[s] = Lv.d.np();
+            }
+            c->shape[g][l][0] = pick_shape(c, [&](const dim3& blk) {
+                const int keep = c->shape[g][l][0];
+                for (int sh = 0; sh < kNumShapes; ++sh)
+                    if ((int)blk.x == kShapes[sh][0] && (int)blk.y == kShapes[sh][1]) c->shape[g][l][0] = sh;
+                gsweep<T>(c, a, l, 1, nrhs);
+                c->shape[g][l][0] = keep;
+            });
+            // restriction (grid = level l+1) and prolongation (grid = level l)
+            GArgs<T> rt = gbase<T>(c, kinds, ns, l + 1, false);
+            GArgs<T> pt = gbase<T>(c, kinds, ns, l, true);
+            for (int s = 0; s < ns; ++s) {
+                Level& Lv = c->blk[kinds[s]].lev[l];
+                Level& Cv = c->blk[kinds[s]].lev[l + 1];
+                rt.dc[s] = Lv.d;
+                rt.f[s] = (const cplx<T>*)Lv.r; rt.vf[s] = Lv.d.np();
+                rt.out[s] = (cplx<T>*)Cv.f; rt.vo[s] = Cv.d.np();
+                pt.f[s] = (const cplx<T>*)Cv.e; pt.vf[s] = Cv.d.np();
+                pt.out[s] = (cplx<T>*)Lv.u; pt.vo[s] = Lv.d.np();
+            }
+            c->shape[g][l][1] = pick_shape(c, [&](const dim3& blk) {
+                if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, true>), ggrid(rt, blk), blk, 0, c->s, rt, nrhs);
+                else hipLaunchKernelGGL((k_gtransfer<T, 3, true>), ggrid(rt, blk), blk, 0, c->s, rt, nrhs);
+                HIPCHK(hipGetLastError());
+            });
+            c->shape[g][l][2] = pick_shape(c, [&](const dim3& blk) {
+                if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, false>), ggrid(pt, blk), blk, 0, c->s, pt, nrhs);
+                else hipLaunchKernelGGL((k_gtransfer<T, 3, false>), ggrid(pt, blk), blk, 0, c->s, pt, nrhs);
+                HIPCHK(hipGetLastError());
+            });
+        }
+    }
+    HIPCHK(hipStreamSynchronize(c->s));
+    c->timer_mask = saved_mask;
+    c->tuned_nrhs = nrhs;
+    tune_cache_store(c, sig);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,6 +1123,7 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
     const int m = c->o.restart;
     ensure_krylov(c, nrhs, m);
     ensure_mg_workspace(c, nrhs);     // no allocation may happen inside a graph capture
+    maybe_autotune<T>(c, nrhs);
     const int64_t n = c->ndof;
     const int64_t vstep = (int64_t)nrhs * n;    // distance between basis vectors
     cplx<T>* Z = (cplx<T>*)c->Z;
@@ -1194,6 +1372,7 @@ void eh_default_opts(eh_opts* o) {
     o->gamma0 = 0.01 * M_PI;
     o->intergrid = 0;
     o->graphs = 1;
+    o->autotune = 1;
 }
 
 const char* eh_last_error(const eh_ctx* c) {
@@ -1228,6 +1407,7 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
     if (o.abc_width < 0) { g_create_error = "abc_width must be >= 0"; return EH_ERR_ARG; }
     if (o.intergrid != 0 && o.intergrid != 1) { g_create_error = "intergrid must be 0 (full) or 1 (mixed)"; return EH_ERR_ARG; }
     if (o.graphs != 0 && o.graphs != 1) { g_create_error = "graphs must be 0 or 1"; return EH_ERR_ARG; }
+    if (o.autotune != 0 && o.autotune != 1) { g_create_error = "autotune must be 0 or 1"; return EH_ERR_ARG; }
     if (!(o.alpha >= 0.0) || !std::isfinite(o.alpha)) { g_create_error = "alpha must be >= 0"; return EH_ERR_ARG; }
     int64_t ncell = 1;
     for (int a = 0; a < dim; ++a) {
@@ -1419,9 +1599,11 @@ eh_status eh_apply_preconditioner(eh_ctx* c, const void* r, void* z, int nrhs) {
     if (!r || !z || nrhs < 1) return fail(c, EH_ERR_ARG, "invalid buffers or nrhs");
     try {
         if (c->o.mg_precision == 64) {
+            maybe_autotune<double>(c, nrhs);
             apply_M<double>(c, (const c128*)r, c->ndof, z, c->ndof, nrhs);
         } else {
             ensure_tmpT(c, (int64_t)nrhs * c->ndof);
+            maybe_autotune<float>(c, nrhs);
             apply_M<float>(c, (const c128*)r, c->ndof, c->tmpT, c->ndof, nrhs);
             const int64_t tot = (int64_t)nrhs * c->ndof;
             hipLaunchKernelGGL((k_cast<double, float>), dim3(lin_grid(tot, 256, 8192)), dim3(256), 0, c->s, tot,

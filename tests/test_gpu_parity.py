@@ -319,3 +319,26 @@ def test_graph_replay_equals_eager():
     for x, its in res[1:]:
         assert its == res[0][1]
         assert np.array_equal(x, res[0][0])
+
+
+@pytest.mark.parametrize("n", [(96, 64), (16, 8, 8)])
+def test_autotuned_shapes_do_not_change_results(n):
+    """The launch-shape autotuner changes only workgroup shapes: the solve
+    and the preconditioner give bitwise the same results with it on or
+    off, for one and for three right-hand sides."""
+    say("autotune vs fixed shapes", n)
+    out = []
+    for tune in (False, True):
+        kw = dict(intergrid="mixed", nu=(2, 2)) if len(n) == 3 else {}
+        gpu, s = make(n, seed=15, levels=3, alpha=0.5, mg_precision=32, autotune=tune, **kw)
+        r = crand((3, s.ndof), 16)
+        z3 = gpu.apply_preconditioner(to_dev(r)).cpu().numpy()
+        z1 = gpu.apply_preconditioner(to_dev(r[:1])).cpu().numpy()
+        x, info = gpu.solve(to_dev(r[:2]), tol=1e-7, maxit=300)
+        out.append((z3, z1, x.cpu().numpy(), [i["iters"] for i in info]))
+        gpu.close()
+    for a, b in zip(out[0], out[1]):
+        if isinstance(a, list):
+            assert a == b
+        else:
+            assert np.array_equal(a, b)
