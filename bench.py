@@ -62,6 +62,28 @@ def cpu_baseline(wl, iters_ref, n_iters):
     }
 
 
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, or None when none was recorded for that
+    kernel class or the kernel sources changed since (sha256 mismatch)."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.txt")):
+        try:
+            rec = json.load(open(path))
+        except (OSError, ValueError):
+            continue
+        if rec.get("kernel_class") != kernel:
+            continue
+        h = hashlib.sha256()
+        for f in rec["source_files"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +98,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB with torch before the solves (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this build "
@@ -126,6 +150,12 @@ def main():
         log(f"timed {steps} solves in {dt:.3f} s, iters {[i[0]['iters'] for i in infos]}")
         return dt, infos, kt
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)       # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"workload {wl.name}: n={wl.n} omega={wl.omega:.4f} levels={wl.levels} alpha={wl.alpha}")
     t_setup = time.perf_counter()
     s32 = make(32)
@@ -179,7 +209,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-        "traffic": None,
+        "traffic": recorded_traffic(kernel),
         "launches": launches,
         "avg_us": avg_ms * 1e3,
         "algorithmic_bytes_per_launch": nbytes / max(launches, 1),

@@ -186,17 +186,19 @@ k_sub(int64_t n, const c128* __restrict__ a, const c128* __restrict__ b, c128* _
         out[p] = a[p] - b[p];
 }
 
-// x[r] += sum_i y[r][i] Z_i[r]   (Z in the multigrid precision)
+// x[r] += sum_{i < mcount} y[r][i] Z_i[r]   (Z in the multigrid precision;
+// only the mcount columns built in this cycle are read -- later columns may
+// hold stale or uninitialised data; y has row stride mstride)
 template <class T>
 __global__ void __launch_bounds__(256)
-k_xupdate(int64_t n, int m, int nrhs, const cplx<T>* __restrict__ Z, const c128* __restrict__ y,
-          c128* __restrict__ x) {
+k_xupdate(int64_t n, int mcount, int mstride, int nrhs, const cplx<T>* __restrict__ Z,
+          const c128* __restrict__ y, c128* __restrict__ x) {
     const int r = blockIdx.y;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
         c128 s = x[(int64_t)r * n + p];
-        for (int i = 0; i < m; ++i)
-            s = s + y[r * m + i] * ccast<double>(Z[((int64_t)i * nrhs + r) * n + p]);
+        for (int i = 0; i < mcount; ++i)
+            s = s + y[r * mstride + i] * ccast<double>(Z[((int64_t)i * nrhs + r) * n + p]);
         x[(int64_t)r * n + p] = s;
     }
 }

@@ -155,6 +155,7 @@ struct eh_ctx {
     int graph_nrhs = -1;
     bool capturing = false;
     hipStream_t solve_stream = nullptr;
+    hipEvent_t order_event = nullptr;      // orders the solve stream after the user's
     // launch shapes per block group (0: H_p, 1: shear blocks), level and
     // kernel kind (0: sweeps/residuals, 1: restriction, 2: prolongation)
     int shape[2][kMaxLevels][3] = {};
@@ -181,6 +182,8 @@ struct eh_ctx {
 
 namespace {
 
+// Events for timing only: without the system-scope fence, recording an event
+// does not write back and invalidate the caches around the kernel it brackets.
 hipEvent_t take_event(eh_ctx* c) {
     if (!c->event_pool.empty()) {
         hipEvent_t e = c->event_pool.back();
@@ -188,7 +191,7 @@ hipEvent_t take_event(eh_ctx* c) {
         return e;
     }
     hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     return e;
 }
 
@@ -1296,8 +1299,8 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
         if (mmax > 0) {
             c128* dy = c->dsmall + (size_t)6 * nrhs * (m + 2);
             HIPCHK(hipMemcpyAsync(dy, ydev.data(), (size_t)nrhs * m * sizeof(c128), hipMemcpyHostToDevice, c->s));
-            Timed tm(c, KC_KRYLOV, (double)nrhs * n * (2 * sizeof(c128) + m * sizeof(cplx<T>)));
-            hipLaunchKernelGGL((k_xupdate<T>), dim3(lin_grid(n, 256, 2048), nrhs), dim3(256), 0, c->s, n, m, nrhs,
+            Timed tm(c, KC_KRYLOV, (double)nrhs * n * (2 * sizeof(c128) + mmax * sizeof(cplx<T>)));
+            hipLaunchKernelGGL((k_xupdate<T>), dim3(lin_grid(n, 256, 2048), nrhs), dim3(256), 0, c->s, n, mmax, m, nrhs,
                                (const cplx<T>*)Z, dy, x);
             HIPCHK(hipGetLastError());
         }
@@ -1338,6 +1341,7 @@ eh_status from_hip(eh_ctx* c, const HipError& e) {
 void destroy_all(eh_ctx* c) {
     drop_graphs(c);
     if (c->solve_stream) { (void)hipStreamDestroy(c->solve_stream); c->solve_stream = nullptr; }
+    if (c->order_event) { (void)hipEventDestroy(c->order_event); c->order_event = nullptr; }
     for (auto& r : c->timer_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     c->timer_recs.clear();
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
@@ -1699,10 +1703,9 @@ eh_status eh_solve(eh_ctx* c, const void* b, void* x, int nrhs, double tol, int 
         // captured on the legacy default stream), ordered after the user's
         // stream by an event; the host waits for it before returning
         if (!c->solve_stream) HIPCHK(hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking));
-        hipEvent_t ev = take_event(c);
-        HIPCHK(hipEventRecord(ev, user));
-        HIPCHK(hipStreamWaitEvent(c->solve_stream, ev, 0));
-        c->event_pool.push_back(ev);
+        if (!c->order_event) HIPCHK(hipEventCreateWithFlags(&c->order_event, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(c->order_event, user));
+        HIPCHK(hipStreamWaitEvent(c->solve_stream, c->order_event, 0));
         c->s = c->solve_stream;
         eh_status st;
         if (c->o.mg_precision == 64) st = solve_impl<double>(c, (const c128*)b, (c128*)x, nrhs, tol, maxit, info);

@@ -342,3 +342,60 @@ def test_autotuned_shapes_do_not_change_results(n):
             assert a == b
         else:
             assert np.array_equal(a, b)
+
+
+def test_edge_cases():
+    """Zero right-hand side -> x = 0 in 0 iterations; maxit = 0 -> x = 0,
+    not converged; one level (the coarsest direct solve on the whole grid)
+    -> exact block solves, one FGMRES iteration on a constant medium with
+    constant attenuation; a bad receiver index is rejected."""
+    say("edge cases")
+    from paper_2411_15897_amd import ElasticHelmholtz, EhelmError
+    n = (16, 16)
+    gpu, s = make(n, seed=17, levels=2, alpha=0.3)
+    b = np.zeros((2, s.ndof), dtype=np.complex128)
+    b[1, 5] = 1.0
+    x, info = gpu.solve(to_dev(b), tol=1e-6, maxit=100)
+    xs = x.cpu().numpy()
+    assert np.all(xs[0] == 0) and info[0]["iters"] == 0 and info[0]["converged"]
+    assert info[1]["converged"]
+    x, info = gpu.solve(to_dev(b[1:]), tol=1e-6, maxit=0)
+    assert np.all(x.cpu().numpy() == 0) and not info[0]["converged"]
+    rec = torch.tensor([s.ndof + 3], dtype=torch.int64, device="cuda")
+    with pytest.raises(EhelmError):
+        gpu.misfit(to_dev(b[1:]), rec, to_dev(np.zeros((1, 1), np.complex128)))
+    gpu.close()
+    vp, vs, rho = W.constant_medium(n, 2.0, 1.0, 1.0)
+    exact = ElasticHelmholtz(n, (1.0, 1.0), vp, vs, rho, 0.6, levels=1, alpha=0.0, mg_precision=64,
+                             abc_width=0, abc_sides=0)
+    bb = np.zeros((1, exact.ndof), dtype=np.complex128)
+    bb[0, exact.field_sizes[0] + 100] = -1.0
+    x, info = exact.solve(to_dev(bb), tol=1e-10, maxit=10)
+    assert info[0]["iters"] == 1 and info[0]["relres_true"] < 1e-10
+    exact.close()
+
+
+def test_preconditioner_and_solve_full_size_1024():
+    """At the 1024 x 1024 benchmark size and settings (6 levels, V(1,2),
+    alpha 0.6): the FP64-multigrid preconditioner against the oracle's
+    V-cycle preconditioner, and the complex64 solve's true residual
+    recomputed by the oracle."""
+    say("full-size preconditioner and solve 1024^2")
+    from paper_2411_15897_amd import ElasticHelmholtz
+    wl = W.config(2)
+    kw = dict(levels=wl.levels, alpha=wl.alpha, restart=wl.restart, abc_width=wl.abc_width,
+              abc_sides=wl.abc_sides)
+    s = ElasticSystem(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, wl.abc_width, wl.abc_sides)
+    M = BlockAcoustic(s, alpha=wl.alpha, solver="mg", levels=wl.levels, cycle="V")
+    r = crand(s.ndof, 18)
+    g64 = ElasticHelmholtz(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, mg_precision=64, **kw)
+    z = g64.apply_preconditioner(to_dev(r)).cpu().numpy()
+    g64.close()
+    assert rel(z, M.apply(r)) <= 1e-10
+    g32 = ElasticHelmholtz(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, mg_precision=32, **kw)
+    b = W.point_source_rhs(wl.n, wl.h, wl.sources)
+    x, info = g32.solve(to_dev(b), tol=1e-6, maxit=2000)
+    g32.close()
+    rr = np.linalg.norm(b[0] - s.apply_H(x.cpu().numpy()[0])) / np.linalg.norm(b[0])
+    say(f"  iters {info[0]['iters']} oracle-recomputed relres {rr:.2e}")
+    assert info[0]["converged"] and rr < 1e-6
