@@ -135,8 +135,13 @@ eh_status eh_block_dims(const eh_ctx *ctx, int block, int level, int64_t *out);
  * FGMRES(restart) (Section 2.2, flexible GMRES), starting from x = 0,
  * stopping each right-hand side when ||b - H x||/||b|| < tol or after maxit
  * preconditioner applications.  b, x: complex128 device buffers of
- * nrhs*ndof entries.  info: host array of nrhs entries (may be NULL).
- * Returns EH_NOT_CONVERGED if any right-hand side missed tol. */
+ * nrhs*ndof entries.  info: host array of nrhs entries (may be NULL);
+ * relres_true is recomputed in FP64 from the returned x.  The Arnoldi
+ * bookkeeping runs on the device; iteration counts may differ by one from
+ * an implementation with modified Gram-Schmidt (this one uses classical
+ * Gram-Schmidt applied twice).  Returns EH_NOT_CONVERGED if any right-hand
+ * side missed tol, EH_ERR_STATE if a non-finite value appeared (x is then
+ * unspecified).  Synchronises. */
 eh_status eh_solve(eh_ctx *ctx, const void *b, void *x, int nrhs, double tol,
                    int maxit, eh_info *info);
 

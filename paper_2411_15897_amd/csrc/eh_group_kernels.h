@@ -398,7 +398,8 @@ k_gdense(DenseArgs da, GArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// coupling g_k = r_k - B_k^T e_p for every shear block (eq. prec)
+// coupling g_k = r_k - B_k^T e_p for every shear block (eq. prec); r_k is
+// rs[r * rss] times the stored vector when rs is given
 
 struct CoupleArgs {
     int ns;
@@ -409,6 +410,8 @@ struct CoupleArgs {
     void* g[GMAX];
     int64_t vg[GMAX];
     double ih[GMAX];
+    const double* rs;        // optional per-RHS scale of ru (stride rss)
+    int64_t rss;
 };
 
 template <class T>
@@ -432,7 +435,8 @@ k_gcouple(CoupleArgs a, Dims dc, const cplx<T>* __restrict__ ep, int nrhs, int64
         c128 gr = mk(0.0, 0.0);
         if (chi >= 0) gr = gr + ccast<double>(ep[r * ve + chi]);
         if (clo >= 0) gr = gr - ccast<double>(ep[r * ve + clo]);
-        g[r * vg + p] = ccast<T>(ru[r * vr + p] - ihk * gr);
+        const double sr = a.rs ? a.rs[r * a.rss] : 1.0;
+        g[r * vg + p] = ccast<T>(sr * ru[r * vr + p] - ihk * gr);
     }
 }
 

@@ -7,7 +7,8 @@
 //      - p / (lambda + mu).
 //  k_distribute: t = B r_u - A_p r_p (eq. mixed-distributed) with
 //      A_p r = B B^T (mu r) - w^2 rho (1 - i gamma/w) r (eq. Ap), written in
-//      the multigrid precision.
+//      the multigrid precision.  With rs given, the input of RHS r is
+//      rs[r * rss] times the stored vector (an unnormalised Krylov column).
 //
 // Same launch shape as the multigrid kernels.
 #pragma once
@@ -88,7 +89,7 @@ k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
              const c128* __restrict__ r2, const c128* __restrict__ rp,
              const double* __restrict__ mu, const c128* __restrict__ mcell, double om2,
              double ih0, double ih1, double ih2, cplx<T>* __restrict__ t, int nrhs,
-             int64_t vs_in, int64_t vs_out) {
+             int64_t vs_in, int64_t vs_out, const double* __restrict__ rs, int64_t rss) {
     EH_POINT_INDEX(dc)
     const int64_t f0 = ((int64_t)k * dc.g[1] + j) * (dc.g[0] + 1) + i;
     const int64_t f1 = ((int64_t)k * (dc.g[1] + 1) + j) * dc.g[0] + i;
@@ -122,7 +123,8 @@ k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
             lap = lap + ihs[a] * s;
         }
         const c128 Apr = lap - om2 * (mc * pc);
-        const c128 tv = mk(-div.re - Apr.re, -div.im - Apr.im);
+        const double sr = rs ? rs[r * rss] : 1.0;
+        const c128 tv = mk(sr * (-div.re - Apr.re), sr * (-div.im - Apr.im));
         t[r * vs_out + p] = ccast<T>(tv);
     }
 }

@@ -1,8 +1,9 @@
 // Host driver of the C-ABI library: setup of the operator and of the
 // multigrid hierarchies, the multigrid cycle schedule, the block-acoustic
 // preconditioner and the flexible GMRES iteration.  Every arithmetic step
-// of the solve runs in the kernels included below; the host only sequences
-// launches and runs the (m+1) x m Hessenberg least-squares update.
+// of the solve, the Hessenberg least-squares update included, runs in the
+// kernels included below; the host sequences launches and reads a status
+// record per Arnoldi step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,6 +42,11 @@ struct HipError {
     } while (0)
 
 struct ArgError {
+    std::string msg;
+};
+
+// A solve met a non-finite value (EH_ERR_STATE; the context stays usable).
+struct StateError {
     std::string msg;
 };
 
@@ -136,8 +142,14 @@ struct eh_ctx {
     c128* W = nullptr;            // nrhs * ndof
     c128* partial = nullptr;
     c128* dsmall = nullptr;       // small device arrays (coefs, results)
-    double* dscale = nullptr;
     int kry_nblk = 0;
+    // device-side Arnoldi state and the host-visible status records
+    // ([m+1][nrhs]: slot j for step j, slot m for a cycle start), one
+    // completion event per slot
+    ArnState arn{};
+    ArnStatus* arn_host = nullptr;    // pinned host memory
+    ArnStatus* arn_dev = nullptr;     // the same memory as the device sees it
+    std::vector<hipEvent_t> arn_ev;
     void* tmpT = nullptr;         // nrhs * ndof multigrid precision (preconditioner I/O)
     int64_t tmpT_elems = 0;
     std::vector<void*> allocs;
@@ -999,8 +1011,13 @@ void apply_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs
 }
 
 // z = P^{-1} D_L r: r complex128 (stride vr), z multigrid precision (stride vz)
+//
+// With rs given, the input of RHS q is rs[q * rss] times the stored r (an
+// unnormalised Krylov column); the preconditioner is linear, so the scale
+// is applied where r is read.
 template <class T>
-void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs) {
+void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs, const double* rs = nullptr,
+             int64_t rss = 0) {
     ensure_mg_workspace(c, nrhs);
     const int d = c->dim;
     Block& Bp = c->blk[d];
@@ -1011,11 +1028,13 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
     if (d == 2)
         hipLaunchKernelGGL((k_distribute<T, 2>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, r + c->off[0],
                            r + c->off[1], r2, r + c->off[d], c->mu, c->mcell, c->omega * c->omega,
-                           1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell);
+                           1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell, rs,
+                           rss);
     else
         hipLaunchKernelGGL((k_distribute<T, 3>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, r + c->off[0],
                            r + c->off[1], r2, r + c->off[d], c->mu, c->mcell, c->omega * c->omega,
-                           1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell);
+                           1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell, rs,
+                           rss);
     HIPCHK(hipGetLastError());
     }
     cplx<T>* Z = (cplx<T>*)z;
@@ -1035,6 +1054,8 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
     CoupleArgs ca{};
     ca.ns = d;
     ca.maxg2 = 1;
+    ca.rs = rs;
+    ca.rss = rss;
     double by = 0.0;
     for (int k = 0; k < d; ++k) {
         Level& Lk = c->blk[k].lev[0];
@@ -1069,19 +1090,68 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
 // ---------------------------------------------------------------------------
 // Krylov helpers
 
+void free_arn_status(eh_ctx* c) {
+    if (c->arn_host) (void)hipHostFree(c->arn_host);
+    c->arn_host = nullptr;
+    c->arn_dev = nullptr;
+}
+
 void ensure_krylov(eh_ctx* c, int nrhs, int m) {
     if (nrhs <= c->kry_nrhs && m <= c->kry_m) return;
     HIPCHK(hipStreamSynchronize(c->s));
     drop_graphs(c);
     c->release(c->V); c->release(c->Z); c->release(c->W); c->release(c->partial);
-    c->release(c->dsmall); c->release(c->dscale);
+    c->release(c->dsmall);
+    c->release(c->arn.sv);
+    free_arn_status(c);
     c->V = c->alloc<c128>((size_t)(m + 1) * nrhs * c->ndof);
     c->Z = c->alloc<char>((size_t)m * nrhs * c->ndof * c->csize());
     c->W = c->alloc<c128>((size_t)nrhs * c->ndof);
     c->kry_nblk = (int)std::max<int64_t>(1, (c->ndof + KRY_E * KRY_THREADS - 1) / (KRY_E * KRY_THREADS));
     c->partial = c->alloc<c128>((size_t)c->kry_nblk * nrhs * 2 * (m + 1));
-    c->dsmall = c->alloc<c128>((size_t)5 * nrhs * 2 * (m + 2));
-    c->dscale = c->alloc<double>(nrhs);
+    c->dsmall = c->alloc<c128>((size_t)6 * nrhs * (m + 2));
+    // Arnoldi state: one allocation carved into 16-byte aligned arrays
+    const size_t R = nrhs, M = m;
+    const size_t sizes[15] = {R * (M + 1) * sizeof(double), sizeof(double), R * M * M * sizeof(c128),
+                              R * M * sizeof(c128), R * M * (M + 1) * sizeof(c128), R * M * sizeof(double),
+                              R * M * sizeof(c128), R * (M + 1) * sizeof(c128), R * M * sizeof(c128),
+                              R * sizeof(double), R * sizeof(double), R * sizeof(int), R * sizeof(int),
+                              R * sizeof(int), R * sizeof(int)};
+    size_t total16 = 0;
+    for (size_t b : sizes) total16 += (b + 15) / 16;
+    char* base = (char*)c->alloc<c128>(total16);
+    int ti = 0;
+    auto take = [&]() { char* p = base; base += (sizes[ti++] + 15) / 16 * 16; return p; };
+    ArnState& A = c->arn;
+    A.m = m;
+    A.nrhs = nrhs;
+    A.sv = (double*)take();     // first: the allocation's base (released through it)
+    A.tol = (double*)take();
+    A.gram = (c128*)take();
+    A.hcol = (c128*)take();
+    A.R = (c128*)take();
+    A.cs = (double*)take();
+    A.sn = (c128*)take();
+    A.g = (c128*)take();
+    A.y = (c128*)take();
+    A.bnorm = (double*)take();
+    A.est = (double*)take();
+    A.jr = (int*)take();
+    A.act = (int*)take();
+    A.its = (int*)take();
+    A.done = (int*)take();
+    void* hp = nullptr;
+    HIPCHK(hipHostMalloc(&hp, (M + 1) * R * sizeof(ArnStatus), hipHostMallocMapped | hipHostMallocCoherent));
+    c->arn_host = (ArnStatus*)hp;
+    void* dp = nullptr;
+    HIPCHK(hipHostGetDevicePointer(&dp, hp, 0));
+    c->arn_dev = (ArnStatus*)dp;
+    std::memset(hp, 0, (M + 1) * R * sizeof(ArnStatus));
+    while (c->arn_ev.size() < M + 1) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->arn_ev.push_back(e);
+    }
     c->kry_nrhs = nrhs;
     c->kry_m = m;
 }
@@ -1089,38 +1159,27 @@ void ensure_krylov(eh_ctx* c, int nrhs, int m) {
 // Gram-Schmidt pass over columns [0, m): MODE as in k_gs.  coef/out are
 // device arrays [nrhs][m] (out: [nrhs][1] for norms).
 template <int MODE>
-void gs_pass(eh_ctx* c, int m, int nrhs, const c128* V, c128* w, const c128* coef, c128* out) {
+void gs_pass(eh_ctx* c, int m, int nrhs, const c128* V, const c128* w, const c128* coef, c128* out,
+             c128* wout = nullptr) {
     const int nblk = c->kry_nblk;
     const double vecs = (MODE == 0 || MODE == 4) ? m + 1 : (MODE == 3 ? 1 : m + 2);
     Timed tm(c, KC_KRYLOV, vecs * nrhs * c->ndof * sizeof(c128));
     hipLaunchKernelGGL((k_gs<MODE>), dim3(nblk, nrhs), dim3(KRY_THREADS), 0, c->s, c->ndof, m, nrhs, V, w,
-                       coef, c->partial);
+                       coef, c->partial, wout);
     HIPCHK(hipGetLastError());
     const int mm = (MODE == 0 || MODE == 1) ? m : (MODE == 4 ? 2 * m : 1);
     hipLaunchKernelGGL(k_reduce_partials, dim3(mm, nrhs), dim3(256), 0, c->s, nblk, mm, nrhs, c->partial, out);
     HIPCHK(hipGetLastError());
 }
 
-void norms(eh_ctx* c, const c128* w, int nrhs, std::vector<double>& out) {
-    c128* d = c->dsmall;
-    gs_pass<3>(c, 1, nrhs, nullptr, const_cast<c128*>(w), nullptr, d);
-    std::vector<c128> h(nrhs);
-    HIPCHK(hipMemcpyAsync(h.data(), d, nrhs * sizeof(c128), hipMemcpyDeviceToHost, c->s));
-    HIPCHK(hipStreamSynchronize(c->s));
-    out.resize(nrhs);
-    for (int r = 0; r < nrhs; ++r) out[r] = std::sqrt(h[r].re);
-}
-
-void scale_into(eh_ctx* c, const c128* w, c128* v, const std::vector<double>& s, int nrhs) {
-    HIPCHK(hipMemcpyAsync(c->dscale, s.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->s));
-    Timed tm(c, KC_KRYLOV, 2.0 * nrhs * c->ndof * sizeof(c128));
-    hipLaunchKernelGGL(k_scale, dim3(lin_grid(c->ndof, 256, 2048), nrhs), dim3(256), 0, c->s, c->ndof, nrhs,
-                       c->dscale, w, v);
-    HIPCHK(hipGetLastError());
-}
-
-typedef std::complex<double> cd;
-
+// Flexible GMRES(m) with right preconditioning, x_0 = 0.  Every Arnoldi
+// step -- z_j = M v_j, w = H z_j, CGS2 against the basis and the Hessenberg
+// update -- runs on the device (replayed from a HIP graph when enabled); the
+// host reads the status record of step j-1 while step j runs and waits for
+// step j itself only when the estimate is about to cross the tolerance, so
+// at most one step is queued beyond convergence (it then acts on inactive
+// right-hand sides only: scale 0, no column counted).  A cycle start
+// computes r = b - H x in FP64, so the last start gives the true residual.
 template <class T>
 eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, int maxit, eh_info* info) {
     const int m = c->o.restart;
@@ -1130,57 +1189,60 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
     const int64_t n = c->ndof;
     const int64_t vstep = (int64_t)nrhs * n;    // distance between basis vectors
     cplx<T>* Z = (cplx<T>*)c->Z;
-    std::vector<double> bnorm, beta;
-    norms(c, b, nrhs, bnorm);
+    ArnState S = c->arn;
+    S.nrhs = nrhs;
+    ArnStatus* hs = c->arn_host;
+    ArnStatus* ds = c->arn_dev;
+    c128* d1 = c->dsmall;
+    c128* d2 = c->dsmall + (size_t)2 * nrhs * (m + 2);
+    c128* d3 = c->dsmall + (size_t)4 * nrhs * (m + 2);
+    const unsigned rgrid = (unsigned)((nrhs + 63) / 64);
+    // predicted estimate below this multiple of tol: wait for the step
+    constexpr double kNear = 3.0;
     HIPCHK(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(c128), c->s));
-    std::vector<int> done(nrhs, 0), its(nrhs, 0);
-    std::vector<double> est(nrhs, 1.0);
-    for (int r = 0; r < nrhs; ++r) if (bnorm[r] == 0.0) { done[r] = 1; est[r] = 0.0; }
     int total = 0;
     bool first = true;
-    std::vector<cd> Hh((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), cs((size_t)nrhs * m),
-        sn((size_t)nrhs * m);
-    std::vector<int> jr(nrhs, 0), active(nrhs, 0);
-    std::vector<c128> h1((size_t)nrhs * 2 * m), hcol((size_t)nrhs * m), nr(nrhs);
-    std::vector<cd> Gm((size_t)nrhs * m * m);
-    std::vector<c128> ydev((size_t)nrhs * m);
-    while (total < maxit) {
-        // r = b - H x
+    auto status = [&](int slot) { return hs + (size_t)slot * nrhs; };
+    auto check_bad = [&](const ArnStatus* st) {
+        for (int r = 0; r < nrhs; ++r)
+            if (st[r].bad) throw StateError{"non-finite value in the Arnoldi process"};
+    };
+    auto any_active = [&](const ArnStatus* st) {
+        for (int r = 0; r < nrhs; ++r)
+            if (st[r].active) return true;
+        return false;
+    };
+    for (;;) {
+        // r = b - H x into stored column 0; its norm starts the cycle
         if (first) {
-            HIPCHK(hipMemcpyAsync(c->W, b, (size_t)nrhs * n * sizeof(c128), hipMemcpyDeviceToDevice, c->s));
+            HIPCHK(hipMemcpyAsync(c->V, b, (size_t)vstep * sizeof(c128), hipMemcpyDeviceToDevice, c->s));
         } else {
-            apply_H<double>(c, x, n, c->V, n, nrhs);      // V_0 slot as scratch
-            hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, b, c->V, c->W);
+            apply_H<double>(c, x, n, c->W, n, nrhs);
+            hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, b, c->W, c->V);
             HIPCHK(hipGetLastError());
         }
+        gs_pass<3>(c, 1, nrhs, nullptr, c->V, nullptr, d3);
+        hipLaunchKernelGGL(k_arn_start, dim3(rgrid), dim3(64), 0, c->s, S, (const c128*)d3, first ? 1 : 0, tol,
+                           ds + (size_t)m * nrhs);
+        HIPCHK(hipGetLastError());
         first = false;
-        norms(c, c->W, nrhs, beta);
-        bool any = false;
-        std::vector<double> sc(nrhs, 0.0);
-        for (int r = 0; r < nrhs; ++r) {
-            if (!done[r] && beta[r] / bnorm[r] < tol) { done[r] = 1; est[r] = beta[r] / bnorm[r]; }
-            if (!std::isfinite(beta[r])) { c->err = "non-finite residual"; return EH_ERR_STATE; }
-            active[r] = !done[r];
-            if (active[r]) { any = true; sc[r] = 1.0 / beta[r]; }
-            jr[r] = 0;
-            for (int q = 0; q <= m; ++q) g[(size_t)r * (m + 1) + q] = 0.0;
-            g[(size_t)r * (m + 1)] = beta[r];
-        }
-        if (!any) break;
-        scale_into(c, c->W, c->V, sc, nrhs);
-        int j = 0;
-        for (; j < m && total < maxit; ++j) {
+        HIPCHK(hipStreamSynchronize(c->s));
+        check_bad(status(m));
+        if (!any_active(status(m)) || total >= maxit) break;
+        int steps = 0;
+        for (int j = 0; j < m && total < maxit; ++j) {
             c128* Vj = c->V + (int64_t)j * vstep;
             cplx<T>* Zj = Z + (int64_t)j * vstep;
-            c128* d1 = c->dsmall;
-            c128* d2 = c->dsmall + (size_t)2 * nrhs * (m + 2);
-            c128* d3 = c->dsmall + (size_t)4 * nrhs * (m + 2);
-            // One Arnoldi step on the device: z_j = M v_j, w = H z_j, and the
-            // first Gram-Schmidt pass (h1 = V^H w and the Gram column V^H v_j).
             auto body = [&]() {
-                apply_M<T>(c, Vj, n, Zj, n, nrhs);
+                apply_M<T>(c, Vj, n, Zj, n, nrhs, S.sv + j, m + 1);
                 apply_H<T>(c, Zj, n, c->W, n, nrhs);
                 gs_pass<4>(c, j + 1, nrhs, c->V, c->W, nullptr, d1);
+                hipLaunchKernelGGL(k_arn_coef, dim3(nrhs), dim3(64), 0, c->s, S, j, (const c128*)d1, d2);
+                HIPCHK(hipGetLastError());
+                gs_pass<2>(c, j + 1, nrhs, c->V, c->W, d2, d3, Vj + vstep);
+                hipLaunchKernelGGL(k_arn_givens, dim3(rgrid), dim3(64), 0, c->s, S, j, (const c128*)d3,
+                                   ds + (size_t)j * nrhs);
+                HIPCHK(hipGetLastError());
             };
             if (c->o.graphs && c->timer_mask == 0) {
                 if (c->graph_nrhs != nrhs || (int)c->graphs.size() != m) {
@@ -1209,118 +1271,51 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
             } else {
                 body();
             }
+            HIPCHK(hipEventRecord(c->arn_ev[j], c->s));
             ++total;
-            // Classical Gram-Schmidt with one reorthogonalisation (CGS2) in two
-            // passes: the first gives h1 = V^H w and the newest Gram column
-            // V^H v_j; the second-pass coefficients follow exactly from
-            // h2 = V^H (w - V h1) = h1 - G h1 with G = V^H V, so the update
-            // w <- w - V (h1 + h2) and ||w|| take one more pass.
-            HIPCHK(hipMemcpyAsync(h1.data(), d1, (size_t)nrhs * 2 * (j + 1) * sizeof(c128), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipStreamSynchronize(c->s));
-            for (int r = 0; r < nrhs; ++r) {
-                const c128* hr = &h1[(size_t)r * 2 * (j + 1)];
-                for (int i = 0; i <= j; ++i)     // Gram column j: G[i][j] = v_i^H v_j
-                    Gm[((size_t)r * m + j) * m + i] = cd(hr[j + 1 + i].re, hr[j + 1 + i].im);
-                for (int i = 0; i <= j; ++i) {
-                    cd gh = 0.0;
-                    for (int q = 0; q <= j; ++q) {
-                        // G[i][q] = v_i^H v_q; stored by column q (q >= i) or conj of column i
-                        const cd gi = (q >= i) ? Gm[((size_t)r * m + q) * m + i]
-                                               : std::conj(Gm[((size_t)r * m + i) * m + q]);
-                        gh += gi * cd(hr[q].re, hr[q].im);
-                    }
-                    const cd tot = 2.0 * cd(hr[i].re, hr[i].im) - gh;
-                    hcol[(size_t)r * (j + 1) + i] = mk(tot.real(), tot.imag());
-                }
+            ++steps;
+            if (j == m - 1 || total >= maxit) break;
+            // Is step j+1 needed?  Known: the status after step j-1 (the
+            // cycle start for j = 0); step j is still running.
+            const ArnStatus* known = status(j == 0 ? m : j - 1);
+            if (j > 0) HIPCHK(hipEventSynchronize(c->arn_ev[j - 1]));
+            check_bad(known);
+            if (!any_active(known)) break;
+            const ArnStatus* before = j >= 2 ? status(j - 2) : (j == 1 ? status(m) : nullptr);
+            bool near = true;
+            for (int r = 0; r < nrhs && near; ++r) {
+                if (!known[r].active) continue;
+                double ratio = 1.0;
+                if (before && before[r].est > 0.0) ratio = std::min(1.0, known[r].est / before[r].est);
+                if (known[r].est * ratio >= kNear * tol) near = false;
             }
-            HIPCHK(hipMemcpyAsync(d2, hcol.data(), (size_t)nrhs * (j + 1) * sizeof(c128), hipMemcpyHostToDevice, c->s));
-            gs_pass<2>(c, j + 1, nrhs, c->V, c->W, d2, d3);
-            HIPCHK(hipMemcpyAsync(nr.data(), d3, (size_t)nrhs * sizeof(c128), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipStreamSynchronize(c->s));
-            bool any_active = false;
-            std::vector<double> s2(nrhs, 0.0);
-            for (int r = 0; r < nrhs; ++r) {
-                if (!active[r]) continue;
-                cd* col = &Hh[((size_t)r * m + j) * (m + 1)];
-                for (int i = 0; i <= j; ++i)
-                    col[i] = cd(hcol[(size_t)r * (j + 1) + i].re, hcol[(size_t)r * (j + 1) + i].im);
-                const double hn = std::sqrt(std::max(0.0, nr[r].re));
-                double w0 = 0.0;
-                for (int i = 0; i <= j; ++i) w0 += std::norm(col[i]);
-                w0 = std::sqrt(w0 + hn * hn);
-                col[j + 1] = hn;
-                // previous rotations
-                for (int i = 0; i < j; ++i) {
-                    const cd ci = cs[(size_t)r * m + i], si = sn[(size_t)r * m + i];
-                    const cd a = col[i], bb = col[i + 1];
-                    col[i] = ci * a + si * bb;
-                    col[i + 1] = -std::conj(si) * a + ci * bb;
-                }
-                // new rotation zeroing col[j+1]
-                const cd a = col[j];
-                const double bb = std::abs(col[j + 1]);
-                const double nu = std::sqrt(std::norm(a) + bb * bb);
-                cd ci, si;
-                if (std::abs(a) == 0.0) { ci = 0.0; si = 1.0; }
-                else { ci = std::abs(a) / nu; si = (a / std::abs(a)) * bb / nu; }
-                cs[(size_t)r * m + j] = ci;
-                sn[(size_t)r * m + j] = si;
-                col[j] = ci * a + si * col[j + 1];
-                col[j + 1] = 0.0;
-                cd* gr = &g[(size_t)r * (m + 1)];
-                gr[j + 1] = -std::conj(si) * gr[j];
-                gr[j] = ci * gr[j];
-                jr[r] = j + 1;
-                its[r] += 1;
-                est[r] = std::abs(gr[j + 1]) / bnorm[r];
-                const bool brk = hn <= 1e-14 * w0;
-                if (!std::isfinite(est[r])) { c->err = "non-finite Arnoldi coefficient"; return EH_ERR_STATE; }
-                if (est[r] < tol || brk) active[r] = 0;
-                else { s2[r] = 1.0 / hn; any_active = true; }
+            if (near) {
+                HIPCHK(hipEventSynchronize(c->arn_ev[j]));
+                check_bad(status(j));
+                if (!any_active(status(j))) break;
             }
-            if (!any_active || j == m - 1 || total >= maxit) { ++j; break; }
-            scale_into(c, c->W, c->V + (int64_t)(j + 1) * vstep, s2, nrhs);
         }
-        // x += Z y, y from the triangular system R y = g
-        int mmax = 0;
-        std::fill(ydev.begin(), ydev.end(), mk(0.0, 0.0));
-        for (int r = 0; r < nrhs; ++r) {
-            const int jj = jr[r];
-            if (jj == 0) continue;
-            mmax = std::max(mmax, jj);
-            std::vector<cd> y(jj);
-            for (int i = jj - 1; i >= 0; --i) {
-                cd s = g[(size_t)r * (m + 1) + i];
-                for (int q = i + 1; q < jj; ++q) s -= Hh[((size_t)r * m + q) * (m + 1) + i] * y[q];
-                y[i] = s / Hh[((size_t)r * m + i) * (m + 1) + i];
-            }
-            for (int i = 0; i < jj; ++i) ydev[(size_t)r * m + i] = mk(y[i].real(), y[i].imag());
-        }
-        if (mmax > 0) {
-            c128* dy = c->dsmall + (size_t)6 * nrhs * (m + 2);
-            HIPCHK(hipMemcpyAsync(dy, ydev.data(), (size_t)nrhs * m * sizeof(c128), hipMemcpyHostToDevice, c->s));
-            Timed tm(c, KC_KRYLOV, (double)nrhs * n * (2 * sizeof(c128) + mmax * sizeof(cplx<T>)));
-            hipLaunchKernelGGL((k_xupdate<T>), dim3(lin_grid(n, 256, 2048), nrhs), dim3(256), 0, c->s, n, mmax, m, nrhs,
-                               (const cplx<T>*)Z, dy, x);
+        // x += Z y with y = R^-1 g of this cycle
+        hipLaunchKernelGGL(k_arn_solve, dim3(rgrid), dim3(64), 0, c->s, S);
+        HIPCHK(hipGetLastError());
+        {
+            Timed tm(c, KC_KRYLOV, (double)nrhs * n * (2 * sizeof(c128) + steps * sizeof(cplx<T>)));
+            hipLaunchKernelGGL((k_xupdate<T>), dim3(lin_grid(n, 256, 2048), nrhs), dim3(256), 0, c->s, n,
+                               (const int*)S.jr, m, nrhs, (const cplx<T>*)Z, (const c128*)S.y, x);
             HIPCHK(hipGetLastError());
         }
     }
-    // true residual in FP64
-    apply_H<double>(c, x, n, c->V, n, nrhs);
-    hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, b, c->V, c->W);
-    HIPCHK(hipGetLastError());
-    std::vector<double> rn;
-    norms(c, c->W, nrhs, rn);
+    // the last cycle start computed the true FP64 residual of x
+    const ArnStatus* fin = status(m);
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
-        const double rel = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
-        const int conv = rel < tol;
+        const int conv = fin[r].rel < tol;
         all = all && conv;
         if (info) {
-            info[r].iters = its[r];
+            info[r].iters = fin[r].its;
             info[r].converged = conv;
-            info[r].relres_true = rel;
-            info[r].relres_est = est[r];
+            info[r].relres_true = fin[r].rel;
+            info[r].relres_est = fin[r].est;
         }
     }
     return all ? EH_OK : EH_NOT_CONVERGED;
@@ -1340,6 +1335,9 @@ eh_status from_hip(eh_ctx* c, const HipError& e) {
 
 void destroy_all(eh_ctx* c) {
     drop_graphs(c);
+    free_arn_status(c);
+    for (auto e : c->arn_ev) (void)hipEventDestroy(e);
+    c->arn_ev.clear();
     if (c->solve_stream) { (void)hipStreamDestroy(c->solve_stream); c->solve_stream = nullptr; }
     if (c->order_event) { (void)hipEventDestroy(c->order_event); c->order_event = nullptr; }
     for (auto& r : c->timer_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
@@ -1713,6 +1711,11 @@ eh_status eh_solve(eh_ctx* c, const void* b, void* x, int nrhs, double tol, int 
         HIPCHK(hipStreamSynchronize(c->s));
         c->s = user;
         return st;
+    } catch (const StateError& e) {
+        const hipError_t se = hipStreamSynchronize(c->s);   // steps may still be queued
+        c->s = user;
+        if (se != hipSuccess) return from_hip(c, HipError{se, "hipStreamSynchronize"});
+        return fail(c, EH_ERR_STATE, e.msg);
     } catch (const HipError& e) {
         c->s = user;
         return from_hip(c, e);

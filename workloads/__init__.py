@@ -200,7 +200,7 @@ def config(k: int, scale: int = 1) -> Workload:
         src = [(1, (n[0] // 2, 1))]
         return Workload("config2_layered_1024", n, h, vp, vs, rho, omega,
                         abc_width=20, abc_sides=abc_all_but_top(2),
-                        sources=src, levels=6, alpha=0.6, restart=10)
+                        sources=src, levels=6, alpha=0.6, restart=6)
     if k == 3:
         n = (512 // scale, 512 // scale)
         vp, vs, rho = layered_medium(n, seed=1)
