@@ -77,6 +77,11 @@ typedef struct {
                                candidate workgroup shape of the sweep, restriction and prolongation kernels
                                per level and block group and keep the fastest (results are unchanged);
                                choices are cached in the file named by $EH_TUNE_CACHE when set */
+    int fused;              /* 1: 2D V(1,nu_post) cycles (nu_post 1 or 2) from a zero guess run each level
+                               as two LDS-tiled launches -- the restricted residual of the first sweep
+                               (down leg) and prolongation + correction + all post-sweeps (up leg) --
+                               for batches of up to 4 right-hand sides; 0: one launch per sweep and
+                               transfer.  Same arithmetic per point; summation order may differ. */
 } eh_opts;
 
 typedef struct {
@@ -172,7 +177,9 @@ eh_status eh_misfit(eh_ctx *ctx, const void *u, const int64_t *rec, int nrec,
  * 1 fine-level residual, 2 coarse-level (Galerkin stencil) sweeps and
  * residuals, 3 restriction, 4 prolongation, 5 coarsest dense solve,
  * 6 operator apply, 7 distributor, 8 coupling, 9 Krylov vector kernels,
- * 10 fine-level first sweep from a zero guess.  While selected, every
+ * 10 fine-level first sweep from a zero guess, 11 fine-level fused down
+ * leg, 12 fine-level fused up leg, 13 coarse-level fused down legs, 14
+ * coarse-level fused up legs.  While selected, every
  * launch of the class is bracketed by two hipEvents on the context's
  * stream.  0 disables timing. */
 eh_status eh_timer_enable(eh_ctx *ctx, unsigned class_mask);

@@ -24,7 +24,7 @@ EXPORTED = [
 KERNEL_CLASSES = {
     "fine_sweep": 0, "fine_resid": 1, "coarse": 2, "restrict": 3, "prolong": 4,
     "dense": 5, "operator": 6, "distribute": 7, "couple": 8, "krylov": 9,
-    "fine_first": 10,
+    "fine_first": 10, "fine_down": 11, "fine_up": 12, "coarse_down": 13, "coarse_up": 14,
 }
 
 
@@ -37,7 +37,7 @@ class EhOpts(ctypes.Structure):
         ("restart", ctypes.c_int), ("abc_width", ctypes.c_int),
         ("abc_sides", ctypes.c_uint), ("gamma0", ctypes.c_double),
         ("intergrid", ctypes.c_int), ("graphs", ctypes.c_int),
-        ("autotune", ctypes.c_int),
+        ("autotune", ctypes.c_int), ("fused", ctypes.c_int),
     ]
 
 

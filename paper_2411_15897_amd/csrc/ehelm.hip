@@ -23,6 +23,7 @@
 #include "eh_setup_kernels.h"
 #include "eh_grad_kernels.h"
 #include "eh_group_kernels.h"
+#include "eh_fused_kernels.h"
 
 using namespace eh;
 
@@ -106,7 +107,11 @@ enum KernelClass {
     KC_COUPLE = 8,
     KC_KRYLOV = 9,       // Gram-Schmidt, scaling, x update
     KC_FINE_FIRST = 10,  // fine-level first sweep from a zero guess
-    KC_COUNT = 11
+    KC_FINE_DOWN = 11,   // fused down leg on the fine level
+    KC_FINE_UP = 12,     // fused up leg on the fine level
+    KC_COARSE_DOWN = 13, // fused down legs on coarse levels
+    KC_COARSE_UP = 14,   // fused up legs on coarse levels
+    KC_COUNT = 15
 };
 
 struct eh_ctx {
@@ -647,6 +652,85 @@ void gcopy(eh_ctx* c, int ns, const void* const* src, const int64_t* vs, void* c
     }
 }
 
+template <class T>
+void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, const int64_t* vf,
+            void* const* out, const int64_t* vo, bool guess, int nrhs);
+
+// Batches up to this size use the fused legs: they re-read the stencil of
+// a tile from cache for every right-hand side, while the unfused kernels
+// keep it in registers across the batch, which pays off for larger ones.
+constexpr int kFuseMaxRhs = 4;
+
+inline bool fused_cycle(const eh_ctx* c, bool guess, int nrhs) {
+    return c->o.fused && c->dim == 2 && c->o.cycle == 0 && c->o.nu_pre == 1 &&
+           (c->o.nu_post == 1 || c->o.nu_post == 2) && !guess && nrhs <= kFuseMaxRhs;
+}
+
+// One level of a V(1, nu2) cycle from a zero guess with the fused legs:
+// f_{l+1} = R (f - X w D^-1 f), the cycle on level l+1, then
+// out = S^nu2 (w D^-1 f + P e_{l+1}).
+template <class T>
+void fused_level(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, const int64_t* vf,
+                 void* const* out, const int64_t* vo, int nrhs) {
+    const bool P = kinds[0] == c->dim;
+    GArgs<T> a = gbase<T>(c, kinds, ns, l, true);
+    const void* cf[GMAX];
+    void* ce[GMAX];
+    int64_t vcv[GMAX];
+    double cbytes = 0.0, vdown = 0.0, vup = 0.0;
+    int gxd = 1, gyd = 1, gxu = 1, gyu = 1;
+    const double cs = sizeof(cplx<T>), rs = sizeof(T);
+    for (int s = 0; s < ns; ++s) {
+        const Block& B = c->blk[kinds[s]];
+        const Level& Lv = B.lev[l];
+        const Level& Cv = B.lev[l + 1];
+        const double np = (double)Lv.d.np(), npc = (double)Cv.d.np();
+        cbytes += l == 0 ? np * (cs + (P ? 1 : c->dim) * rs) : np * (Lv.w.nst() + 1) * cs;
+        vdown += (np + npc) * cs;
+        vup += (2 * np + npc) * cs;
+        cf[s] = Cv.f; ce[s] = Cv.e; vcv[s] = Cv.d.np();
+        gxd = std::max(gxd, (Cv.d.g[0] + FD_CX - 1) / FD_CX);
+        gyd = std::max(gyd, (Cv.d.g[1] + FD_CY - 1) / FD_CY);
+        gxu = std::max(gxu, (Lv.d.g[0] + FU_TX - 1) / FU_TX);
+        gyu = std::max(gyu, (Lv.d.g[1] + FU_TY - 1) / FU_TY);
+    }
+    {
+        for (int s = 0; s < ns; ++s) {
+            a.f[s] = (const cplx<T>*)f[s];
+            a.vf[s] = vf[s];
+            a.out[s] = (cplx<T>*)cf[s];
+            a.vo[s] = vcv[s];
+        }
+        Timed tm(c, l == 0 ? KC_FINE_DOWN : KC_COARSE_DOWN, cbytes + nrhs * vdown);
+        const dim3 g((unsigned)gxd, (unsigned)gyd, (unsigned)ns);
+        if (l == 0) hipLaunchKernelGGL((k_fdown<T, true>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
+        else hipLaunchKernelGGL((k_fdown<T, false>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
+        HIPCHK(hipGetLastError());
+    }
+    gcycle<T>(c, kinds, ns, l + 1, cf, vcv, ce, vcv, false, nrhs);
+    {
+        for (int s = 0; s < ns; ++s) {
+            a.f[s] = (const cplx<T>*)f[s];
+            a.vf[s] = vf[s];
+            a.u[s] = (const cplx<T>*)ce[s];
+            a.vu[s] = vcv[s];
+            a.out[s] = (cplx<T>*)out[s];
+            a.vo[s] = vo[s];
+        }
+        Timed tm(c, l == 0 ? KC_FINE_UP : KC_COARSE_UP, cbytes + nrhs * vup);
+        const dim3 g((unsigned)gxu, (unsigned)gyu, (unsigned)ns);
+        const bool two = c->o.nu_post == 2;
+        if (l == 0) {
+            if (two) hipLaunchKernelGGL((k_fup<T, true, 2>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
+            else hipLaunchKernelGGL((k_fup<T, true, 1>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
+        } else {
+            if (two) hipLaunchKernelGGL((k_fup<T, false, 2>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
+            else hipLaunchKernelGGL((k_fup<T, false, 1>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
+        }
+        HIPCHK(hipGetLastError());
+    }
+}
+
 // One cycle on level l for X_l e = f, for the blocks kinds[0..ns).  f[s]
 // has stride vf[s]; the result goes to out[s] (stride vo[s]).  With guess,
 // out[s] holds the initial guess.
@@ -690,6 +774,10 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
         return;
     }
     const int nu1 = c->o.nu_pre, nu2 = c->o.nu_post;
+    if (fused_cycle(c, guess, nrhs)) {
+        fused_level<T>(c, kinds, ns, l, f, vf, out, vo, nrhs);
+        return;
+    }
     const void* cur[GMAX];
     int64_t vcur[GMAX];
     int nb = 0;   // next internal buffer: 0 -> u, 1 -> t
@@ -1375,6 +1463,7 @@ void eh_default_opts(eh_opts* o) {
     o->intergrid = 0;
     o->graphs = 1;
     o->autotune = 1;
+    o->fused = 1;
 }
 
 const char* eh_last_error(const eh_ctx* c) {
@@ -1410,6 +1499,7 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
     if (o.intergrid != 0 && o.intergrid != 1) { g_create_error = "intergrid must be 0 (full) or 1 (mixed)"; return EH_ERR_ARG; }
     if (o.graphs != 0 && o.graphs != 1) { g_create_error = "graphs must be 0 or 1"; return EH_ERR_ARG; }
     if (o.autotune != 0 && o.autotune != 1) { g_create_error = "autotune must be 0 or 1"; return EH_ERR_ARG; }
+    if (o.fused != 0 && o.fused != 1) { g_create_error = "fused must be 0 or 1"; return EH_ERR_ARG; }
     if (!(o.alpha >= 0.0) || !std::isfinite(o.alpha)) { g_create_error = "alpha must be >= 0"; return EH_ERR_ARG; }
     int64_t ncell = 1;
     for (int a = 0; a < dim; ++a) {

@@ -48,7 +48,7 @@ class ElasticHelmholtz:
     def __init__(self, n, h, vp, vs, rho, omega, *, levels=3, cycle="V",
                  nu=(1, 2), damping=(0.8, 0.8, 0.3), alpha=0.1,
                  mg_precision=32, restart=20, abc_width=20, abc_sides=None,
-                 gamma0=0.01 * math.pi, intergrid="full", graphs=True, autotune=True,
+                 gamma0=0.01 * math.pi, intergrid="full", graphs=True, autotune=True, fused=True,
                  stream=None):
         L = N.lib()
         self._lib = L
@@ -72,6 +72,7 @@ class ElasticHelmholtz:
         opts.intergrid = {"full": 0, "mixed": 1}[intergrid] if isinstance(intergrid, str) else int(intergrid)
         opts.graphs = 1 if graphs else 0
         opts.autotune = 1 if autotune else 0
+        opts.fused = 1 if fused else 0
         self.opts = opts
         arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel()) for a in (vp, vs, rho)]
         ncell = int(np.prod(self.n))

@@ -302,7 +302,7 @@ def test_graph_replay_equals_eager():
     for graphs, timers in ((True, False), (True, False), (False, False), (True, True)):
         gpu, s = make(n, seed=13, levels=4, alpha=0.4, mg_precision=32, restart=8, graphs=graphs)
         if timers:
-            gpu.timer_enable(["coarse", "fine_sweep"])
+            gpu.timer_enable(["coarse_up", "fine_up"])
         b = np.zeros((2, s.ndof), dtype=np.complex128)
         b[0, s.face_sizes[0] + 100] = -1.0
         b[1] = crand(s.ndof, 14)
@@ -312,7 +312,7 @@ def test_graph_replay_equals_eager():
         assert torch.equal(x1, x2)
         assert [i["iters"] for i in i1] == [i["iters"] for i in i2]
         if timers:
-            nl, ms, by = gpu.timer_read("coarse")
+            nl, ms, by = gpu.timer_read("coarse_up")
             assert nl > 0 and ms > 0 and by > 0
         res.append((x1.cpu().numpy(), [i["iters"] for i in i1]))
         gpu.close()
@@ -399,3 +399,38 @@ def test_preconditioner_and_solve_full_size_1024():
     rr = np.linalg.norm(b[0] - s.apply_H(x.cpu().numpy()[0])) / np.linalg.norm(b[0])
     say(f"  iters {info[0]['iters']} oracle-recomputed relres {rr:.2e}")
     assert info[0]["converged"] and rr < 1e-6
+
+
+@pytest.mark.parametrize("intergrid", ["full", "mixed"])
+@pytest.mark.parametrize("nu2", [2, 1])
+@pytest.mark.parametrize("n,levels", [((96, 40), 3), ((200, 72), 4)])
+def test_fused_legs_match_oracle_and_unfused(n, levels, nu2, intergrid):
+    """The LDS-tiled down/up legs of a 2D V(1, nu2) cycle: every block's
+    cycle against the oracle (FP64 to 1e-10) and against the one-launch-per-
+    sweep kernels (FP64 to 1e-12, complex64 to 1e-5), on grids that leave
+    partial tiles on every level; the preconditioner with 2 right-hand sides
+    (fused) against 5 (above the fused batch limit, unfused)."""
+    say("fused legs", n, levels, nu2, intergrid)
+    alpha, nu, damping = 0.3, (1, nu2), (0.8, 0.8, 0.3)
+    kw = dict(levels=levels, alpha=alpha, nu=nu, damping=damping, intergrid=intergrid)
+    g64, s = make(n, seed=19, mg_precision=64, **kw)
+    u64, _ = make(n, seed=19, mg_precision=64, fused=False, **kw)
+    g32, _ = make(n, seed=19, mg_precision=32, **kw)
+    u32, _ = make(n, seed=19, mg_precision=32, fused=False, **kw)
+    for b in range(3):
+        X = s.H_p(alpha) if b == 2 else s.A_block(b, alpha)
+        nodal = (False, False) if b == 2 else face_nodal(2, b)
+        mg = Hierarchy(X, s.n, nodal, levels, damping=damping, nu=nu, intergrid=intergrid)
+        f = crand(X.shape[0], 50 + b)
+        ft = to_dev(f)
+        e64 = g64.block_cycle(b, ft).cpu().numpy()
+        assert rel(e64, mg(f)) <= 1e-10, b
+        assert rel(e64, u64.block_cycle(b, ft).cpu().numpy()) <= 1e-12, b
+        assert rel(g32.block_cycle(b, ft).cpu().numpy(), u32.block_cycle(b, ft).cpu().numpy()) <= 1e-5, b
+    r = crand((5, s.ndof), 60)
+    z2 = g64.apply_preconditioner(to_dev(r[:2])).cpu().numpy()
+    z5 = g64.apply_preconditioner(to_dev(r)).cpu().numpy()
+    for k in range(2):
+        assert rel(z2[k], z5[k]) <= 1e-12
+    for g in (g64, u64, g32, u32):
+        g.close()
