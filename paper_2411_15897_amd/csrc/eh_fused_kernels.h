@@ -26,7 +26,8 @@
 // Galerkin stencils because the setup never couples outside the grid), so
 // the stencil sums need no bounds tests.
 //
-// Launch: blockDim 256 (1D), gridDim (tiles x, tiles y, slots of the group).
+// Launch: blockDim (threads of the tile configuration, 1D), gridDim (tiles
+// x, tiles y, slots of the group).
 #pragma once
 
 #include "eh_common.h"
@@ -35,17 +36,47 @@
 
 namespace eh {
 
-constexpr int FUSE_THREADS = 256;
-// down leg: coarse tile; up leg: fine tile
-constexpr int FD_CX = 32, FD_CY = 8;
-constexpr int FU_TX = 64, FU_TY = 8;
+// Tile configurations (x extent, y extent, threads): the down leg's tile
+// is in coarse points, the up leg's in fine points.  Large tiles amortise
+// the halo on big levels; small ones give the few-thousand-point levels
+// enough workgroups and keep every phase to about one round of loads per
+// thread.  The autotuner picks one per level and block group.  The phase
+// loops stay rolled: on small levels each compute unit runs a workgroup or
+// two, so the kernel's instruction fetch from a cold cache is part of its
+// latency, and unrolled code costs more there than it gains on big levels.
+struct FCfg {
+    int x, y, threads;
+};
+constexpr FCfg kFDown[] = {{32, 8, 256}, {32, 8, 512}, {16, 8, 256}, {8, 4, 128}};
+constexpr FCfg kFUp[] = {{64, 16, 1024}, {64, 8, 512}, {32, 8, 256}, {16, 8, 128}};
+constexpr int kFCfgs = 4;
 constexpr int FUSE_MAXW = 2;
 // LDS elements: down = staged u0 (support + halo) + residual of the support;
 // up = u~ (tile + 2 halos) + first sweep (tile + 1 halo)
-constexpr int FD_LDS = (2 * FD_CX + 2 + 2 * FUSE_MAXW) * (2 * FD_CY + 2 + 2 * FUSE_MAXW) +
-                       (2 * FD_CX + 2) * (2 * FD_CY + 2);
-constexpr int FU_LDS = (FU_TX + 4 * FUSE_MAXW) * (FU_TY + 4 * FUSE_MAXW) +
-                       (FU_TX + 2 * FUSE_MAXW) * (FU_TY + 2 * FUSE_MAXW);
+__host__ __device__ constexpr int fd_lds(int cx, int cy) {
+    return (2 * cx + 2 + 2 * FUSE_MAXW) * (2 * cy + 2 + 2 * FUSE_MAXW) + (2 * cx + 2) * (2 * cy + 2);
+}
+__host__ __device__ constexpr int fu_lds(int tx, int ty) {
+    return (tx + 4 * FUSE_MAXW) * (ty + 4 * FUSE_MAXW) + (tx + 2 * FUSE_MAXW) * (ty + 2 * FUSE_MAXW);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumber the tiles of one slot so that every XCD gets a contiguous
+// run of tiles in row-major order: neighbouring tiles, whose halos
+// overlap, then read them through the same L2.  A bijection on the tiles.
+__device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
+    const int n = gridDim.x * gridDim.y;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    int t = b;
+    if (n >= 16) {
+        const int m = (n + 7) / 8;             // tiles per XCD, rounded up
+        const int full = n - 8 * (m - 1);      // XCDs that get m tiles
+        const int r = b % 8, q = b / 8;
+        t = r < full ? r * m + q : full * m + (r - full) * (m - 1) + q;
+    }
+    ty = t / gridDim.x;
+    tx = t - ty * gridDim.x;
+}
 
 // First-sweep factor w / D at point p of level l: stored on coarse levels,
 // from the fine diagonal on level 0.
@@ -55,42 +86,65 @@ __device__ __forceinline__ cplx<T> fuse_sc(const GArgs<T>& a, int slot, int64_t 
     return a.dinv[slot][p];
 }
 
-// X u at point (gx, gy) (linear index p) with u taken from an LDS array S
-// of row pitch SX at local index l.  Stored stencils: X u = sum_o coef_o u;
-// fine level: X u = D u - sum_nb c_nb u_nb (FineCoef).
-template <class T, bool FINE, int KIND, int WX, int WY, int SX>
-__device__ __forceinline__ cplx<T> fuse_apply(const GArgs<T>& a, int slot, const Dims& d, int gx, int gy,
-                                              int64_t p, const cplx<T>* S, int l) {
-    if (FINE) {
-        FineCoef<T, KIND, 2> c;
-        c.load(d, gx, gy, 0, p, a.w[slot][0], a.w[slot][1], a.w[slot][2], a.ih[0], a.ih[1], a.ih[2]);
-        const cplx<T> offs = c.cp[0] * S[l + 1] + c.cm[0] * S[l - 1] + c.cp[1] * S[l + SX] + c.cm[1] * S[l - SX];
-        return a.D[slot][p] * S[l] - offs;
-    }
-    const int64_t np = d.np();
-    const cplx<T>* __restrict__ coef = a.coef[slot];
-    cplx<T> xu = czero<T>();
+// The operator at one point with its coefficients in registers: stored
+// stencils, X u = sum_o coef_o u; fine level, X u = D u - sum_nb c_nb u_nb
+// (FineCoef).  u comes from an LDS array of row pitch SX.  Every point of
+// every phase goes through these same functions, so a point's value does
+// not depend on which tile, or which phase of a tile, computes it.  The up
+// leg keeps its own tile point's operator for both sweeps and every
+// right-hand side.
+template <class T, bool FINE, int KIND, int WX, int WY>
+struct PointOp {
+    static constexpr int NST = (2 * WX + 1) * (2 * WY + 1);
+    cplx<T> cf[FINE ? 1 : NST];
+    FineCoef<T, KIND, 2> fc;
+    cplx<T> D, sc;
+    __device__ __forceinline__ void load(const GArgs<T>& a, int slot, const Dims& d, int gx, int gy, int64_t p) {
+        sc = fuse_sc<T, FINE>(a, slot, p);
+        if (FINE) {
+            fc.load(d, gx, gy, 0, p, a.w[slot][0], a.w[slot][1], a.w[slot][2], a.ih[0], a.ih[1], a.ih[2]);
+            D = a.D[slot][p];
+        } else {
+            const int64_t np = d.np();
 #pragma unroll
-    for (int oy = -WY; oy <= WY; ++oy)
-#pragma unroll
-        for (int ox = -WX; ox <= WX; ++ox) {
-            const int o = (oy + WY) * (2 * WX + 1) + (ox + WX);
-            xu = xu + coef[o * np + p] * S[l + oy * SX + ox];
+            for (int o = 0; o < (FINE ? 1 : NST); ++o) cf[o] = a.coef[slot][o * np + p];
         }
-    return xu;
-}
+    }
+    // X u with u from an LDS array of row pitch SX at local index l
+    template <int SX>
+    __device__ __forceinline__ cplx<T> apply(const cplx<T>* S, int l) const {
+        if (FINE) {
+            const cplx<T> offs =
+                fc.cp[0] * S[l + 1] + fc.cm[0] * S[l - 1] + fc.cp[1] * S[l + SX] + fc.cm[1] * S[l - SX];
+            return D * S[l] - offs;
+        }
+        cplx<T> xu = czero<T>();
+#pragma unroll
+        for (int oy = -WY; oy <= WY; ++oy)
+#pragma unroll
+            for (int ox = -WX; ox <= WX; ++ox)
+                xu = xu + cf[FINE ? 0 : (oy + WY) * (2 * WX + 1) + (ox + WX)] * S[l + oy * SX + ox];
+        return xu;
+    }
+    // one damped Jacobi update u + w D^-1 (f - X u) at local index l
+    template <int SX>
+    __device__ __forceinline__ cplx<T> sweep(const cplx<T>* S, int l, cplx<T> fp) const {
+        return S[l] + sc * (fp - apply<SX>(S, l));
+    }
+};
 
 // ---------------------------------------------------------------------------
 // down leg: a.d = level l, a.dc = level l+1, a.f = f_l (vf), a.out = f_{l+1} (vo)
 
-template <class T, bool FINE, int KIND, int WX, int WY, int NM, bool MIXED>
-__device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* lds, int nrhs) {
+template <class T, bool FINE, int KIND, int WX, int WY, int NM, bool MIXED, int CX, int CY, int NT>
+__device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* lds, int nrhs, int tile_x,
+                                          int tile_y) {
     const Dims d = a.d[slot], dc = a.dc[slot];
-    const int X0 = blockIdx.x * FD_CX, Y0 = blockIdx.y * FD_CY;
+    const int X0 = tile_x * CX, Y0 = tile_y * CY;
     if (X0 >= dc.g[0] || Y0 >= dc.g[1]) return;       // uniform per workgroup
     const int nx = d.g[0], ny = d.g[1];
-    constexpr int RX = 2 * FD_CX + 2, RY = 2 * FD_CY + 2;   // fine support of the tile
-    constexpr int UX = RX + 2 * WX, UY = RY + 2 * WY;       // plus one stencil width
+    constexpr int RX = 2 * CX + 2, RY = 2 * CY + 2;   // fine support of the tile
+    constexpr int UX = RX + 2 * WX, UY = RY + 2 * WY; // plus one stencil width
     const int rx0 = 2 * X0 - 1, ry0 = 2 * Y0 - 1;
     cplx<T>* U = lds;
     cplx<T>* RR = lds + UX * UY;
@@ -99,7 +153,10 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
     for (int r = 0; r < nrhs; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
         if (r > 0) __syncthreads();                 // LDS of the previous RHS consumed
-        for (int q = threadIdx.x; q < UX * UY; q += FUSE_THREADS) {
+#pragma unroll 1
+        for (int it = 0; it < (UX * UY + NT - 1) / NT; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q >= UX * UY) break;
             const int uy = q / UX, ux = q - uy * UX;
             const int gx = rx0 - WX + ux, gy = ry0 - WY + uy;
             cplx<T> v = czero<T>();
@@ -110,21 +167,29 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
             U[q] = v;
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < RX * RY; q += FUSE_THREADS) {
+#pragma unroll 1
+        for (int it = 0; it < (RX * RY + NT - 1) / NT; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q >= RX * RY) break;
             const int ry = q / RX, rx = q - ry * RX;
             const int gx = rx0 + rx, gy = ry0 + ry;
             cplx<T> v = czero<T>();
             if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
                 const int64_t p = (int64_t)gy * nx + gx;
                 const int l = (ry + WY) * UX + (rx + WX);
-                v = f[p] - fuse_apply<T, FINE, KIND, WX, WY, UX>(a, slot, d, gx, gy, p, U, l);
+                PointOp<T, FINE, KIND, WX, WY> op;
+                op.load(a, slot, d, gx, gy, p);
+                v = f[p] - op.template apply<UX>(U, l);
             }
             RR[q] = v;
         }
         __syncthreads();
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
-        for (int q = threadIdx.x; q < FD_CX * FD_CY; q += FUSE_THREADS) {
-            const int cy = q / FD_CX, cx = q - cy * FD_CX;
+#pragma unroll 1
+        for (int it = 0; it < (CX * CY + NT - 1) / NT; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q >= CX * CY) break;
+            const int cy = q / CX, cx = q - cy * CX;
             const int I = X0 + cx, J = Y0 + cy;
             if (I >= dc.g[0] || J >= dc.g[1]) continue;
             // first fine index of the support, local to the region
@@ -141,54 +206,73 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
     }
 }
 
-template <class T, bool FINE>
-__global__ void __launch_bounds__(FUSE_THREADS)
+template <class T, bool FINE, int CFG>
+__global__ void __launch_bounds__(kFDown[CFG].threads)
 k_fdown(GArgs<T> a, int nrhs) {
-    __shared__ cplx<T> lds[FD_LDS];
+    constexpr int CX = kFDown[CFG].x, CY = kFDown[CFG].y, NT = kFDown[CFG].threads;
+    __shared__ cplx<T> lds[fd_lds(CX, CY)];
     const int slot = blockIdx.z;
     if (slot >= a.ns) return;
     const int kind = a.kind[slot];           // 0: A_1, 1: A_2, 2: H_p
+    int tx, ty;
+    xcd_tile(tx, ty);
+#define EH_FD(FI, KI, WX, WY, NM, MX) down_body<T, FI, KI, WX, WY, NM, MX, CX, CY, NT>(a, slot, lds, nrhs, tx, ty)
     if (FINE && a.mixed) {
-        if (kind == 2) down_body<T, true, 1, 1, 1, 0, true>(a, slot, lds, nrhs);
-        else if (kind == 0) down_body<T, true, 0, 1, 1, 1, true>(a, slot, lds, nrhs);
-        else down_body<T, true, 0, 1, 1, 2, true>(a, slot, lds, nrhs);
+        if (kind == 2) EH_FD(true, 1, 1, 1, 0, true);
+        else if (kind == 0) EH_FD(true, 0, 1, 1, 1, true);
+        else EH_FD(true, 0, 1, 1, 2, true);
     } else if (FINE) {
-        if (kind == 2) down_body<T, true, 1, 1, 1, 0, false>(a, slot, lds, nrhs);
-        else if (kind == 0) down_body<T, true, 0, 1, 1, 1, false>(a, slot, lds, nrhs);
-        else down_body<T, true, 0, 1, 1, 2, false>(a, slot, lds, nrhs);
+        if (kind == 2) EH_FD(true, 1, 1, 1, 0, false);
+        else if (kind == 0) EH_FD(true, 0, 1, 1, 1, false);
+        else EH_FD(true, 0, 1, 1, 2, false);
     } else if (a.mixed) {
-        if (kind == 2) down_body<T, false, 0, 1, 1, 0, true>(a, slot, lds, nrhs);
-        else if (kind == 0) down_body<T, false, 0, 1, 1, 1, true>(a, slot, lds, nrhs);
-        else down_body<T, false, 0, 1, 1, 2, true>(a, slot, lds, nrhs);
+        if (kind == 2) EH_FD(false, 0, 1, 1, 0, true);
+        else if (kind == 0) EH_FD(false, 0, 1, 1, 1, true);
+        else EH_FD(false, 0, 1, 1, 2, true);
     } else {
-        if (kind == 2) down_body<T, false, 0, 2, 2, 0, false>(a, slot, lds, nrhs);
-        else if (kind == 0) down_body<T, false, 0, 1, 2, 1, false>(a, slot, lds, nrhs);
-        else down_body<T, false, 0, 2, 1, 2, false>(a, slot, lds, nrhs);
+        if (kind == 2) EH_FD(false, 0, 2, 2, 0, false);
+        else if (kind == 0) EH_FD(false, 0, 1, 2, 1, false);
+        else EH_FD(false, 0, 2, 1, 2, false);
     }
+#undef EH_FD
 }
 
 // ---------------------------------------------------------------------------
 // up leg: a.d = level l, a.dc = level l+1, a.f = f_l (vf), a.u = e_{l+1}
 // (vu), a.out = e_l (vo)
 
-template <class T, bool FINE, int KIND, int WX, int WY, int NM, int NU2>
-__device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* lds, int nrhs) {
+template <class T, bool FINE, int KIND, int WX, int WY, int NM, int NU2, int TX, int TY, int NT>
+__device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* lds, int nrhs, int tile_x,
+                                        int tile_y) {
+    static_assert(TX * TY == NT, "one tile point per thread");
     const Dims d = a.d[slot], dc = a.dc[slot];
     const int nx = d.g[0], ny = d.g[1];
-    const int tx0 = blockIdx.x * FU_TX, ty0 = blockIdx.y * FU_TY;
+    const int tx0 = tile_x * TX, ty0 = tile_y * TY;
     if (tx0 >= nx || ty0 >= ny) return;           // uniform per workgroup
     constexpr int HX = NU2 * WX, HY = NU2 * WY;
-    constexpr int AX = FU_TX + 2 * HX, AY = FU_TY + 2 * HY;     // u~
-    constexpr int BX = FU_TX + 2 * WX, BY = FU_TY + 2 * WY;     // first of two sweeps
+    constexpr int AX = TX + 2 * HX, AY = TY + 2 * HY;     // u~
+    constexpr int BX = TX + 2 * WX, BY = TY + 2 * WY;     // first of two sweeps
+    constexpr int RING = BX * BY - TX * TY;               // its points outside the tile
     cplx<T>* A = lds;
     cplx<T>* B = lds + AX * AY;
     const int64_t csy = dc.g[0];
+    // this thread's tile point and its operator, kept for every sweep and RHS
+    const int my_y = threadIdx.x / TX, my_x = threadIdx.x - my_y * TX;
+    const int mgx = tx0 + my_x, mgy = ty0 + my_y;
+    const bool mine = mgx < nx && mgy < ny;
+    const int64_t mp = (int64_t)mgy * nx + mgx;
+    PointOp<T, FINE, KIND, WX, WY> op;
+    if (mine) op.load(a, slot, d, mgx, mgy, mp);
     for (int r = 0; r < nrhs; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
         const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
+        const cplx<T> fmine = mine ? f[mp] : czero<T>();
         if (r > 0) __syncthreads();
-        for (int q = threadIdx.x; q < AX * AY; q += FUSE_THREADS) {
+#pragma unroll 1
+        for (int it = 0; it < (AX * AY + NT - 1) / NT; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q >= AX * AY) break;
             const int ay = q / AX, ax = q - ay * AX;
             const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
             cplx<T> v = czero<T>();
@@ -208,54 +292,77 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
         }
         __syncthreads();
         if (NU2 == 2) {
-            for (int q = threadIdx.x; q < BX * BY; q += FUSE_THREADS) {
-                const int by = q / BX, bx = q - by * BX;
+            // first sweep: the own tile point from registers ...
+            {
+                const int l = (my_y + 2 * WY) * AX + (my_x + 2 * WX);
+                cplx<T> v = czero<T>();
+                if (mine) v = op.template sweep<AX>(A, l, fmine);
+                B[(my_y + WY) * BX + my_x + WX] = v;
+            }
+            // ... and the ring around the tile with coefficients from memory
+#pragma unroll 1
+            for (int it = 0; it < (RING + NT - 1) / NT; ++it) {
+                const int q = threadIdx.x + it * NT;
+                if (q >= RING) break;
+                int bx, by;
+                if (q < 2 * WY * BX) {                       // rows above and below
+                    const int row = q / BX;
+                    bx = q - row * BX;
+                    by = row < WY ? row : TY + row;
+                } else {                                     // columns left and right
+                    const int q2 = q - 2 * WY * BX;
+                    const int row = q2 / (2 * WX), cc = q2 - row * (2 * WX);
+                    by = WY + row;
+                    bx = cc < WX ? cc : TX + cc;
+                }
                 const int gx = tx0 - WX + bx, gy = ty0 - WY + by;
                 cplx<T> v = czero<T>();
                 if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
                     const int64_t p = (int64_t)gy * nx + gx;
                     const int l = (by + WY) * AX + (bx + WX);
-                    const cplx<T> xu = fuse_apply<T, FINE, KIND, WX, WY, AX>(a, slot, d, gx, gy, p, A, l);
-                    v = A[l] + fuse_sc<T, FINE>(a, slot, p) * (f[p] - xu);
+                    PointOp<T, FINE, KIND, WX, WY> rop;
+                    rop.load(a, slot, d, gx, gy, p);
+                    v = rop.template sweep<AX>(A, l, f[p]);
                 }
-                B[q] = v;
+                B[by * BX + bx] = v;
             }
             __syncthreads();
         }
         const cplx<T>* S = NU2 == 2 ? B : A;
         constexpr int SX = NU2 == 2 ? BX : AX;
-        for (int q = threadIdx.x; q < FU_TX * FU_TY; q += FUSE_THREADS) {
-            const int ty = q / FU_TX, tx = q - ty * FU_TX;
-            const int gx = tx0 + tx, gy = ty0 + ty;
-            if (gx >= nx || gy >= ny) continue;
-            const int64_t p = (int64_t)gy * nx + gx;
-            const int l = (ty + WY) * SX + (tx + WX);
-            const cplx<T> xu = fuse_apply<T, FINE, KIND, WX, WY, SX>(a, slot, d, gx, gy, p, S, l);
-            out[p] = S[l] + fuse_sc<T, FINE>(a, slot, p) * (f[p] - xu);
+        constexpr int OX = NU2 == 2 ? WX : HX, OY = NU2 == 2 ? WY : HY;
+        if (mine) {
+            const int l = (my_y + OY) * SX + (my_x + OX);
+            out[mp] = op.template sweep<SX>(S, l, fmine);
         }
     }
 }
 
-template <class T, bool FINE, int NU2>
-__global__ void __launch_bounds__(FUSE_THREADS)
+template <class T, bool FINE, int NU2, int CFG>
+__global__ void __launch_bounds__(kFUp[CFG].threads)
 k_fup(GArgs<T> a, int nrhs) {
-    __shared__ cplx<T> lds[FU_LDS];
+    constexpr int TX = kFUp[CFG].x, TY = kFUp[CFG].y, NT = kFUp[CFG].threads;
+    __shared__ cplx<T> lds[fu_lds(TX, TY)];
     const int slot = blockIdx.z;
     if (slot >= a.ns) return;
     const int kind = a.kind[slot];
+    int tx, ty;
+    xcd_tile(tx, ty);
+#define EH_FU(FI, KI, WX, WY, NM) up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT>(a, slot, lds, nrhs, tx, ty)
     if (FINE) {
-        if (kind == 2) up_body<T, true, 1, 1, 1, 0, NU2>(a, slot, lds, nrhs);
-        else if (kind == 0) up_body<T, true, 0, 1, 1, 1, NU2>(a, slot, lds, nrhs);
-        else up_body<T, true, 0, 1, 1, 2, NU2>(a, slot, lds, nrhs);
+        if (kind == 2) EH_FU(true, 1, 1, 1, 0);
+        else if (kind == 0) EH_FU(true, 0, 1, 1, 1);
+        else EH_FU(true, 0, 1, 1, 2);
     } else if (a.mixed) {
-        if (kind == 2) up_body<T, false, 0, 1, 1, 0, NU2>(a, slot, lds, nrhs);
-        else if (kind == 0) up_body<T, false, 0, 1, 1, 1, NU2>(a, slot, lds, nrhs);
-        else up_body<T, false, 0, 1, 1, 2, NU2>(a, slot, lds, nrhs);
+        if (kind == 2) EH_FU(false, 0, 1, 1, 0);
+        else if (kind == 0) EH_FU(false, 0, 1, 1, 1);
+        else EH_FU(false, 0, 1, 1, 2);
     } else {
-        if (kind == 2) up_body<T, false, 0, 2, 2, 0, NU2>(a, slot, lds, nrhs);
-        else if (kind == 0) up_body<T, false, 0, 1, 2, 1, NU2>(a, slot, lds, nrhs);
-        else up_body<T, false, 0, 2, 1, 2, NU2>(a, slot, lds, nrhs);
+        if (kind == 2) EH_FU(false, 0, 2, 2, 0);
+        else if (kind == 0) EH_FU(false, 0, 1, 2, 1);
+        else EH_FU(false, 0, 2, 1, 2);
     }
+#undef EH_FU
 }
 
 }  // namespace eh

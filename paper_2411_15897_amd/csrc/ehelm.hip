@@ -176,6 +176,9 @@ struct eh_ctx {
     // launch shapes per block group (0: H_p, 1: shear blocks), level and
     // kernel kind (0: sweeps/residuals, 1: restriction, 2: prolongation)
     int shape[2][kMaxLevels][3] = {};
+    // tile configurations of the fused legs per block group and level
+    // (0: down leg, 1: up leg), indices into kFDown / kFUp
+    int fcfg[2][kMaxLevels][2] = {};
     int tuned_nrhs = 0;
 
     template <class P>
@@ -669,16 +672,70 @@ inline bool fused_cycle(const eh_ctx* c, bool guess, int nrhs) {
 // One level of a V(1, nu2) cycle from a zero guess with the fused legs:
 // f_{l+1} = R (f - X w D^-1 f), the cycle on level l+1, then
 // out = S^nu2 (w D^-1 f + P e_{l+1}).
+// Fused down leg on level l with tile configuration cfg: a.d / a.dc = levels
+// l / l+1, a.f = f_l, a.out = f_{l+1}.
+template <class T>
+void launch_fdown(eh_ctx* c, const GArgs<T>& a, int l, int cfg, int nrhs) {
+    const FCfg k = kFDown[cfg];
+    int gx = 1, gy = 1;
+    for (int s = 0; s < a.ns; ++s) {
+        gx = std::max(gx, (a.dc[s].g[0] + k.x - 1) / k.x);
+        gy = std::max(gy, (a.dc[s].g[1] + k.y - 1) / k.y);
+    }
+    const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)a.ns), blk((unsigned)k.threads);
+#define EH_LFD(CF)                                                                          \
+    if (l == 0) hipLaunchKernelGGL((k_fdown<T, true, CF>), g, blk, 0, c->s, a, nrhs);       \
+    else hipLaunchKernelGGL((k_fdown<T, false, CF>), g, blk, 0, c->s, a, nrhs);
+    switch (cfg) {
+        case 0: EH_LFD(0) break;
+        case 1: EH_LFD(1) break;
+        case 2: EH_LFD(2) break;
+        default: EH_LFD(3) break;
+    }
+#undef EH_LFD
+    HIPCHK(hipGetLastError());
+}
+
+// Fused up leg on level l: a.f = f_l, a.u = e_{l+1}, a.out = e_l.
+template <class T>
+void launch_fup(eh_ctx* c, const GArgs<T>& a, int l, int cfg, int nrhs) {
+    const FCfg k = kFUp[cfg];
+    int gx = 1, gy = 1;
+    for (int s = 0; s < a.ns; ++s) {
+        gx = std::max(gx, (a.d[s].g[0] + k.x - 1) / k.x);
+        gy = std::max(gy, (a.d[s].g[1] + k.y - 1) / k.y);
+    }
+    const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)a.ns), blk((unsigned)k.threads);
+    const bool two = c->o.nu_post == 2;
+#define EH_LFU(CF)                                                                                    \
+    if (l == 0) {                                                                                     \
+        if (two) hipLaunchKernelGGL((k_fup<T, true, 2, CF>), g, blk, 0, c->s, a, nrhs);               \
+        else hipLaunchKernelGGL((k_fup<T, true, 1, CF>), g, blk, 0, c->s, a, nrhs);                   \
+    } else {                                                                                          \
+        if (two) hipLaunchKernelGGL((k_fup<T, false, 2, CF>), g, blk, 0, c->s, a, nrhs);              \
+        else hipLaunchKernelGGL((k_fup<T, false, 1, CF>), g, blk, 0, c->s, a, nrhs);                  \
+    }
+    switch (cfg) {
+        case 0: EH_LFU(0) break;
+        case 1: EH_LFU(1) break;
+        case 2: EH_LFU(2) break;
+        default: EH_LFU(3) break;
+    }
+#undef EH_LFU
+    HIPCHK(hipGetLastError());
+}
+
 template <class T>
 void fused_level(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, const int64_t* vf,
                  void* const* out, const int64_t* vo, int nrhs) {
     const bool P = kinds[0] == c->dim;
+    const int grp = group_of(c, kinds[0]);
+    const int lt = std::min(l, kMaxLevels - 1);
     GArgs<T> a = gbase<T>(c, kinds, ns, l, true);
     const void* cf[GMAX];
     void* ce[GMAX];
     int64_t vcv[GMAX];
     double cbytes = 0.0, vdown = 0.0, vup = 0.0;
-    int gxd = 1, gyd = 1, gxu = 1, gyu = 1;
     const double cs = sizeof(cplx<T>), rs = sizeof(T);
     for (int s = 0; s < ns; ++s) {
         const Block& B = c->blk[kinds[s]];
@@ -689,10 +746,6 @@ void fused_level(eh_ctx* c, const int* kinds, int ns, int l, const void* const* 
         vdown += (np + npc) * cs;
         vup += (2 * np + npc) * cs;
         cf[s] = Cv.f; ce[s] = Cv.e; vcv[s] = Cv.d.np();
-        gxd = std::max(gxd, (Cv.d.g[0] + FD_CX - 1) / FD_CX);
-        gyd = std::max(gyd, (Cv.d.g[1] + FD_CY - 1) / FD_CY);
-        gxu = std::max(gxu, (Lv.d.g[0] + FU_TX - 1) / FU_TX);
-        gyu = std::max(gyu, (Lv.d.g[1] + FU_TY - 1) / FU_TY);
     }
     {
         for (int s = 0; s < ns; ++s) {
@@ -702,10 +755,7 @@ void fused_level(eh_ctx* c, const int* kinds, int ns, int l, const void* const* 
             a.vo[s] = vcv[s];
         }
         Timed tm(c, l == 0 ? KC_FINE_DOWN : KC_COARSE_DOWN, cbytes + nrhs * vdown);
-        const dim3 g((unsigned)gxd, (unsigned)gyd, (unsigned)ns);
-        if (l == 0) hipLaunchKernelGGL((k_fdown<T, true>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
-        else hipLaunchKernelGGL((k_fdown<T, false>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
-        HIPCHK(hipGetLastError());
+        launch_fdown<T>(c, a, l, c->fcfg[grp][lt][0], nrhs);
     }
     gcycle<T>(c, kinds, ns, l + 1, cf, vcv, ce, vcv, false, nrhs);
     {
@@ -718,16 +768,7 @@ void fused_level(eh_ctx* c, const int* kinds, int ns, int l, const void* const* 
             a.vo[s] = vo[s];
         }
         Timed tm(c, l == 0 ? KC_FINE_UP : KC_COARSE_UP, cbytes + nrhs * vup);
-        const dim3 g((unsigned)gxu, (unsigned)gyu, (unsigned)ns);
-        const bool two = c->o.nu_post == 2;
-        if (l == 0) {
-            if (two) hipLaunchKernelGGL((k_fup<T, true, 2>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
-            else hipLaunchKernelGGL((k_fup<T, true, 1>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
-        } else {
-            if (two) hipLaunchKernelGGL((k_fup<T, false, 2>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
-            else hipLaunchKernelGGL((k_fup<T, false, 1>), g, dim3(FUSE_THREADS), 0, c->s, a, nrhs);
-        }
-        HIPCHK(hipGetLastError());
+        launch_fup<T>(c, a, l, c->fcfg[grp][lt][1], nrhs);
     }
 }
 
@@ -914,8 +955,9 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
 
 std::string tune_signature(const eh_ctx* c, int nrhs) {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "d%d n%lldx%lldx%lld L%d p%d i%d r%d", c->dim, (long long)c->n[0],
-                  (long long)c->n[1], (long long)c->n[2], c->o.levels, c->o.mg_precision, c->o.intergrid, nrhs);
+    std::snprintf(buf, sizeof(buf), "d%d n%lldx%lldx%lld L%d p%d i%d r%d f%d n%d", c->dim, (long long)c->n[0],
+                  (long long)c->n[1], (long long)c->n[2], c->o.levels, c->o.mg_precision, c->o.intergrid, nrhs,
+                  c->o.fused, c->o.nu_post);
     return buf;
 }
 
@@ -931,24 +973,28 @@ bool tune_cache_load(eh_ctx* c, const std::string& sig) {
         const size_t bar = ln.find(" | ");
         if (bar == std::string::npos || ln.substr(0, bar) != sig) continue;
         const char* q = ln.c_str() + bar + 3;
-        int vals[2 * kMaxLevels * 3];
+        int vals[2 * kMaxLevels * 5];
         int cnt = 0;
         char* end = nullptr;
-        while (cnt < 2 * kMaxLevels * 3) {
+        while (cnt < 2 * kMaxLevels * 5) {
             long v = std::strtol(q, &end, 10);
             if (end == q) break;
             vals[cnt++] = (int)v;
             q = end;
         }
-        const int need = 2 * c->o.levels * 3;
-        if (cnt != need) continue;
+        const int nsh = 2 * c->o.levels * 3;
+        if (cnt != nsh + 2 * c->o.levels * 2) continue;
         bool ok = true;
-        for (int t = 0; t < cnt; ++t) if (vals[t] < 0 || vals[t] >= kNumShapes) ok = false;
+        for (int t = 0; t < cnt; ++t)
+            if (vals[t] < 0 || vals[t] >= (t < nsh ? kNumShapes : kFCfgs)) ok = false;
         if (!ok) continue;
         int t = 0;
         for (int g = 0; g < 2; ++g)
             for (int l = 0; l < c->o.levels; ++l)
                 for (int w = 0; w < 3; ++w) c->shape[g][l][w] = vals[t++];
+        for (int g = 0; g < 2; ++g)
+            for (int l = 0; l < c->o.levels; ++l)
+                for (int w = 0; w < 2; ++w) c->fcfg[g][l][w] = vals[t++];
         found = true;
     }
     std::fclose(fp);
@@ -964,6 +1010,9 @@ void tune_cache_store(const eh_ctx* c, const std::string& sig) {
     for (int g = 0; g < 2; ++g)
         for (int l = 0; l < c->o.levels; ++l)
             for (int w = 0; w < 3; ++w) std::fprintf(fp, " %d", c->shape[g][l][w]);
+    for (int g = 0; g < 2; ++g)
+        for (int l = 0; l < c->o.levels; ++l)
+            for (int w = 0; w < 2; ++w) std::fprintf(fp, " %d", c->fcfg[g][l][w]);
     std::fprintf(fp, "\n");
     std::fclose(fp);
 }
@@ -990,6 +1039,36 @@ int pick_shape(eh_ctx* c, F launch) {
     return best;
 }
 
+// Time `launch(cfg)` for every fused-leg tile configuration; return the
+// fastest.  Candidates alternate launch by launch, so each timed launch
+// follows a different kernel, as in a cycle: on small levels a kernel's
+// time includes fetching its instructions into a cold cache.
+template <class F>
+int pick_cfg(eh_ctx* c, F launch) {
+    hipEvent_t ev[2 * kFCfgs];
+    for (auto& e : ev) e = take_event(c);
+    float tot[kFCfgs] = {};
+    for (int cf = 0; cf < kFCfgs; ++cf) launch(cf);   // warm-up
+    for (int rep = 0; rep < 3; ++rep) {
+        for (int cf = 0; cf < kFCfgs; ++cf) {
+            HIPCHK(hipEventRecord(ev[2 * cf], c->s));
+            launch(cf);
+            HIPCHK(hipEventRecord(ev[2 * cf + 1], c->s));
+        }
+        HIPCHK(hipEventSynchronize(ev[2 * kFCfgs - 1]));
+        for (int cf = 0; cf < kFCfgs; ++cf) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[2 * cf], ev[2 * cf + 1]));
+            tot[cf] += ms;
+        }
+    }
+    for (auto e : ev) c->event_pool.push_back(e);
+    int best = 0;
+    for (int cf = 1; cf < kFCfgs; ++cf)
+        if (tot[cf] < tot[best]) best = cf;
+    return best;
+}
+
 // Pick the workgroup shape of the sweep, restriction and prolongation
 // kernels of every level and block group for this batch size, timing each
 // candidate on the level's own buffers.  Arithmetic per point does not
@@ -1009,6 +1088,36 @@ void maybe_autotune(eh_ctx* c, int nrhs) {
         int ns = 0;
         if (g == 0) kinds[ns++] = c->dim;
         else for (int k = 0; k < c->dim; ++k) kinds[ns++] = k;
+        if (fused_cycle(c, false, nrhs)) {
+            // the fused legs are the only level kernels at this batch size
+            for (int l = 0; l < L; ++l)
+                for (int s = 0; s < ns; ++s) {
+                    Level& Lv = c->blk[kinds[s]].lev[l];
+                    const int64_t tot = Lv.d.np() * nrhs;
+                    for (void* p : {Lv.f, Lv.u, Lv.e})
+                        hipLaunchKernelGGL((k_fill<cplx<T>>), dim3(lin_grid(tot, 256, 4096)), dim3(256), 0, c->s,
+                                           tot, (cplx<T>*)p, mk<T>(T(0.5), T(-0.25)));
+                }
+            HIPCHK(hipGetLastError());
+            for (int l = 0; l + 1 < L; ++l) {
+                GArgs<T> a = gbase<T>(c, kinds, ns, l, true);
+                for (int s = 0; s < ns; ++s) {
+                    Level& Lv = c->blk[kinds[s]].lev[l];
+                    Level& Cv = c->blk[kinds[s]].lev[l + 1];
+                    a.f[s] = (const cplx<T>*)Lv.f; a.vf[s] = Lv.d.np();
+                    a.out[s] = (cplx<T>*)Cv.f; a.vo[s] = Cv.d.np();
+                }
+                c->fcfg[g][l][0] = pick_cfg(c, [&](int cf) { launch_fdown<T>(c, a, l, cf, nrhs); });
+                for (int s = 0; s < ns; ++s) {
+                    Level& Lv = c->blk[kinds[s]].lev[l];
+                    Level& Cv = c->blk[kinds[s]].lev[l + 1];
+                    a.u[s] = (const cplx<T>*)Cv.e; a.vu[s] = Cv.d.np();
+                    a.out[s] = (cplx<T>*)Lv.u; a.vo[s] = Lv.d.np();
+                }
+                c->fcfg[g][l][1] = pick_cfg(c, [&](int cf) { launch_fup<T>(c, a, l, cf, nrhs); });
+            }
+            continue;
+        }
         for (int l = 0; l < L; ++l) {
             for (int s = 0; s < ns; ++s) {
                 Level& Lv = c->blk[kinds[s]].lev[l];
