@@ -253,6 +253,11 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     constexpr int AX = TX + 2 * HX, AY = TY + 2 * HY;     // u~
     constexpr int BX = TX + 2 * WX, BY = TY + 2 * WY;     // first of two sweeps
     constexpr int RING = BX * BY - TX * TY;               // its points outside the tile
+    static_assert(RING <= NT, "at most one ring point per thread");
+    // small operators (fine level, 3x3 stencils) of the ring point are
+    // loaded up front with the own point's, so that every global load of
+    // the kernel is issued before the first barrier
+    constexpr bool RING_EARLY = FINE || (2 * WX + 1) * (2 * WY + 1) <= 9;
     cplx<T>* A = lds;
     cplx<T>* B = lds + AX * AY;
     const int64_t csy = dc.g[0];
@@ -263,16 +268,37 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     const int64_t mp = (int64_t)mgy * nx + mgx;
     PointOp<T, FINE, KIND, WX, WY> op;
     if (mine) op.load(a, slot, d, mgx, mgy, mp);
+    // this thread's ring point (first sweep only)
+    int rbx = 0, rby = 0;
+    {
+        const int q = threadIdx.x;
+        if (q < 2 * WY * BX) {                       // rows above and below the tile
+            const int row = q / BX;
+            rbx = q - row * BX;
+            rby = row < WY ? row : TY + row;
+        } else {                                     // columns left and right
+            const int q2 = q - 2 * WY * BX;
+            const int row = q2 / (2 * WX), cc = q2 - row * (2 * WX);
+            rby = WY + row;
+            rbx = cc < WX ? cc : TX + cc;
+        }
+    }
+    const int rgx = tx0 - WX + rbx, rgy = ty0 - WY + rby;
+    const bool ring = NU2 == 2 && (int)threadIdx.x < RING && rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny;
+    const int64_t rp = (int64_t)rgy * nx + rgx;
+    PointOp<T, FINE, KIND, WX, WY> rop;
+    if (RING_EARLY && ring) rop.load(a, slot, d, rgx, rgy, rp);
     for (int r = 0; r < nrhs; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
         const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
         const cplx<T> fmine = mine ? f[mp] : czero<T>();
+        const cplx<T> fring = ring ? f[rp] : czero<T>();
         if (r > 0) __syncthreads();
-#pragma unroll 1
-        for (int it = 0; it < (AX * AY + NT - 1) / NT; ++it) {
+        // u~ = w D^-1 f + P e over region A
+        auto stage = [&](int it) {
             const int q = threadIdx.x + it * NT;
-            if (q >= AX * AY) break;
+            if (q >= AX * AY) return;
             const int ay = q / AX, ax = q - ay * AX;
             const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
             cplx<T> v = czero<T>();
@@ -289,42 +315,37 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
                 v = fuse_sc<T, FINE>(a, slot, p) * f[p] + pe;
             }
             A[q] = v;
+        };
+        constexpr int NA = (AX * AY + NT - 1) / NT;    // at most 3 rounds
+        if constexpr (FINE) {
+            // few registers per point: all rounds' loads in flight at once
+#pragma unroll
+            for (int it = 0; it < NA; ++it) stage(it);
+        } else {
+#pragma unroll 1
+            for (int it = 0; it < NA; ++it) stage(it);
         }
         __syncthreads();
         if (NU2 == 2) {
-            // first sweep: the own tile point from registers ...
+            // first sweep on the tile (own point) and on the ring around it
             {
                 const int l = (my_y + 2 * WY) * AX + (my_x + 2 * WX);
                 cplx<T> v = czero<T>();
                 if (mine) v = op.template sweep<AX>(A, l, fmine);
                 B[(my_y + WY) * BX + my_x + WX] = v;
             }
-            // ... and the ring around the tile with coefficients from memory
-#pragma unroll 1
-            for (int it = 0; it < (RING + NT - 1) / NT; ++it) {
-                const int q = threadIdx.x + it * NT;
-                if (q >= RING) break;
-                int bx, by;
-                if (q < 2 * WY * BX) {                       // rows above and below
-                    const int row = q / BX;
-                    bx = q - row * BX;
-                    by = row < WY ? row : TY + row;
-                } else {                                     // columns left and right
-                    const int q2 = q - 2 * WY * BX;
-                    const int row = q2 / (2 * WX), cc = q2 - row * (2 * WX);
-                    by = WY + row;
-                    bx = cc < WX ? cc : TX + cc;
-                }
-                const int gx = tx0 - WX + bx, gy = ty0 - WY + by;
+            if ((int)threadIdx.x < RING) {
                 cplx<T> v = czero<T>();
-                if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-                    const int64_t p = (int64_t)gy * nx + gx;
-                    const int l = (by + WY) * AX + (bx + WX);
-                    PointOp<T, FINE, KIND, WX, WY> rop;
-                    rop.load(a, slot, d, gx, gy, p);
-                    v = rop.template sweep<AX>(A, l, f[p]);
+                const int l = (rby + WY) * AX + (rbx + WX);
+                if (ring && RING_EARLY) {
+                    v = rop.template sweep<AX>(A, l, fring);
+                } else if (ring) {
+                    // wide stencils: loaded here, not held across the batch
+                    PointOp<T, FINE, KIND, WX, WY> wop;
+                    wop.load(a, slot, d, rgx, rgy, rp);
+                    v = wop.template sweep<AX>(A, l, fring);
                 }
-                B[by * BX + bx] = v;
+                B[rby * BX + rbx] = v;
             }
             __syncthreads();
         }

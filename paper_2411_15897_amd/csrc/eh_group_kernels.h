@@ -378,7 +378,23 @@ k_gdense(DenseArgs da, GArgs<T> a) {
     double accr[RB], acci[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) { accr[r] = 0.0; acci[r] = 0.0; }
-    for (int c = lane; c < N; c += 64) {
+    // four row segments in flight per lane (the matrix read is the cost)
+    constexpr int U = 4;
+    int c = lane;
+    for (; c + 64 * (U - 1) < N; c += 64 * U) {
+        c128 av[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) av[u] = A[c + 64 * u];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const cplx<T> fv = f[r * vf + c + 64 * u];
+                accr[r] += av[u].re * double(fv.re) - av[u].im * double(fv.im);
+                acci[r] += av[u].re * double(fv.im) + av[u].im * double(fv.re);
+            }
+    }
+    for (; c < N; c += 64) {
         const c128 av = A[c];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {

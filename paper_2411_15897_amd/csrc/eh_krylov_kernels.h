@@ -73,7 +73,7 @@ k_gs(int64_t n, int m, int nrhs, const c128* __restrict__ V, const c128* w,
             for (int e = 0; e < KRY_E; ++e) {
                 const int64_t p = base + e * KRY_THREADS;
                 if (p < n) {
-                    const c128 v = Vt[p];
+                    const c128 v = t == m - 1 ? vl[e] : Vt[p];   // the newest column is in registers
                     ar += v.re * wv[e].re + v.im * wv[e].im;
                     ai += v.re * wv[e].im - v.im * wv[e].re;
                     gr += v.re * vl[e].re + v.im * vl[e].im;

@@ -1040,32 +1040,33 @@ int pick_shape(eh_ctx* c, F launch) {
 }
 
 // Time `launch(cfg)` for every fused-leg tile configuration; return the
-// fastest.  Candidates alternate launch by launch, so each timed launch
-// follows a different kernel, as in a cycle: on small levels a kernel's
-// time includes fetching its instructions into a cold cache.
+// one with the smallest median.  Candidates alternate launch by launch, so
+// each timed launch follows a different kernel, as in a cycle: on small
+// levels a kernel's time includes fetching its instructions into a cold
+// cache, and single launches of a few microseconds are noisy.
 template <class F>
 int pick_cfg(eh_ctx* c, F launch) {
+    constexpr int kReps = 7;
     hipEvent_t ev[2 * kFCfgs];
     for (auto& e : ev) e = take_event(c);
-    float tot[kFCfgs] = {};
+    float t[kFCfgs][kReps] = {};
     for (int cf = 0; cf < kFCfgs; ++cf) launch(cf);   // warm-up
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < kReps; ++rep) {
         for (int cf = 0; cf < kFCfgs; ++cf) {
             HIPCHK(hipEventRecord(ev[2 * cf], c->s));
             launch(cf);
             HIPCHK(hipEventRecord(ev[2 * cf + 1], c->s));
         }
         HIPCHK(hipEventSynchronize(ev[2 * kFCfgs - 1]));
-        for (int cf = 0; cf < kFCfgs; ++cf) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ev[2 * cf], ev[2 * cf + 1]));
-            tot[cf] += ms;
-        }
+        for (int cf = 0; cf < kFCfgs; ++cf) HIPCHK(hipEventElapsedTime(&t[cf][rep], ev[2 * cf], ev[2 * cf + 1]));
     }
     for (auto e : ev) c->event_pool.push_back(e);
     int best = 0;
-    for (int cf = 1; cf < kFCfgs; ++cf)
-        if (tot[cf] < tot[best]) best = cf;
+    float best_ms = 1e30f;
+    for (int cf = 0; cf < kFCfgs; ++cf) {
+        std::sort(t[cf], t[cf] + kReps);
+        if (t[cf][kReps / 2] < best_ms) { best_ms = t[cf][kReps / 2]; best = cf; }
+    }
     return best;
 }
 
@@ -1179,10 +1180,10 @@ void maybe_autotune(eh_ctx* c, int nrhs) {
 template <class Tin>
 void apply_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs) {
     const cplx<Tin>* X = (const cplx<Tin>*)x;
-    const cplx<Tin>* pf = X + c->off[c->dim];
     double coefb = 8.0 * c->ncell;
     for (int k = 0; k < c->dim; ++k) coefb += (double)c->fsize[k] * (8.0 * c->dim + 16.0);
     Timed tm(c, KC_OPERATOR, coefb + (double)nrhs * c->ndof * (sizeof(cplx<Tin>) + sizeof(c128)));
+    const cplx<Tin>* pf = X + c->off[c->dim];
     for (int k = 0; k < c->dim; ++k) {
         const Dims& d = c->dface[k];
         if (c->dim == 2)
