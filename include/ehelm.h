@@ -79,9 +79,9 @@ typedef struct {
                                choices are cached in the file named by $EH_TUNE_CACHE when set */
     int fused;              /* 1: 2D V(1,nu_post) cycles (nu_post 1 or 2) from a zero guess run each level
                                as two LDS-tiled launches -- the restricted residual of the first sweep
-                               (down leg) and prolongation + correction + all post-sweeps (up leg) --
-                               for batches of up to 4 right-hand sides; 0: one launch per sweep and
-                               transfer.  Same arithmetic per point; summation order may differ. */
+                               (down leg) and prolongation + correction + all post-sweeps (up leg);
+                               0: one launch per sweep and transfer.  Same arithmetic per point;
+                               summation order may differ. */
 } eh_opts;
 
 typedef struct {

@@ -659,14 +659,10 @@ template <class T>
 void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, const int64_t* vf,
             void* const* out, const int64_t* vo, bool guess, int nrhs);
 
-// Batches up to this size use the fused legs: they re-read the stencil of
-// a tile from cache for every right-hand side, while the unfused kernels
-// keep it in registers across the batch, which pays off for larger ones.
-constexpr int kFuseMaxRhs = 4;
-
 inline bool fused_cycle(const eh_ctx* c, bool guess, int nrhs) {
+    (void)nrhs;
     return c->o.fused && c->dim == 2 && c->o.cycle == 0 && c->o.nu_pre == 1 &&
-           (c->o.nu_post == 1 || c->o.nu_post == 2) && !guess && nrhs <= kFuseMaxRhs;
+           (c->o.nu_post == 1 || c->o.nu_post == 2) && !guess;
 }
 
 // One level of a V(1, nu2) cycle from a zero guess with the fused legs:
