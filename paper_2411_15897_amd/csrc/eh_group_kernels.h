@@ -168,11 +168,12 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
     const cplx<T>* __restrict__ u = a.u[slot];
     const int64_t vu = a.vu[slot];
     if (NST <= 27) {
-        // stencil and neighbour offsets in registers; missing neighbours get a
-        // zero coefficient and the point's own offset, so the batch loop has
-        // no branches and every coefficient is read once per launch
+        // stencil in registers; a missing neighbour gets a zero coefficient
+        // and reads the point itself, so the batch loop has no branches and
+        // every coefficient is read once per launch.  Neighbour offsets are
+        // recomputed from the (uniform) strides rather than held per lane.
         cplx<T> cf[NST];
-        int off[NST];
+        unsigned okmask = 0;
 #pragma unroll
         for (int oz = -WZ; oz <= WZ; ++oz)
 #pragma unroll
@@ -182,19 +183,27 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
                     const int o = ((oz + WZ) * NY + (oy + WY)) * NX + (ox + WX);
                     const bool ok = (k + oz >= 0) && (k + oz < d.g[2]) && (j + oy >= 0) && (j + oy < d.g[1]) &&
                                     (i + ox >= 0) && (i + ox < d.g[0]);
-                    off[o] = ok ? (int)(oz * sz + oy * sy + ox) : 0;
+                    okmask |= ok ? (1u << o) : 0u;
                     cf[o] = ok ? coef[o * np + p] : czero<T>();
                     if (MODE == 4) {
                         // neighbour's first-sweep factor damp / D_nb folded into the coefficient
-                        cf[o] = cf[o] * (ok ? dinv[p + off[o]] : czero<T>());
+                        cf[o] = cf[o] * (ok ? dinv[p + oz * sz + oy * sy + ox] : czero<T>());
                     }
                 }
-#pragma unroll 2
+#pragma unroll 1
         for (int r = 0; r < nrhs; ++r) {
             const cplx<T>* __restrict__ src = (MODE == 4) ? f + r * vf : u + r * vu;
             cplx<T> xu = czero<T>();
 #pragma unroll
-            for (int o = 0; o < NST; ++o) xu = xu + cf[o] * src[p + off[o]];
+            for (int oz = -WZ; oz <= WZ; ++oz)
+#pragma unroll
+                for (int oy = -WY; oy <= WY; ++oy)
+#pragma unroll
+                    for (int ox = -WX; ox <= WX; ++ox) {
+                        const int o = ((oz + WZ) * NY + (oy + WY)) * NX + (ox + WX);
+                        const int64_t q = ((okmask >> o) & 1u) ? p + oz * sz + oy * sy + ox : p;
+                        xu = xu + cf[o] * src[q];
+                    }
             const cplx<T> fp = f[r * vf + p];
             if (MODE == 1) out[r * vo + p] = src[p] + sc * (fp - xu);
             else if (MODE == 2) out[r * vo + p] = fp - xu;
@@ -241,12 +250,14 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
     }
 }
 
-template <class T, int DIM, int MODE>
+// MIXED is a template parameter so that the 3x3(x3) mixed-intergrid
+// kernels are not sized for the wide full-weighting stencils of 3D.
+template <class T, int DIM, int MODE, bool MIXED>
 __global__ void __launch_bounds__(256)
 k_gstencil(GArgs<T> a, int nrhs) {
     EH_GROUP_POINT(a, d)
     const int kind = a.kind[slot];
-    if (a.mixed) {
+    if (MIXED) {
         stencil_body<T, 1, 1, (DIM == 3 ? 1 : 0), MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
         return;
     }

@@ -629,7 +629,9 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
 #undef EH_GF_M
 #undef EH_GF
     } else {
-#define EH_GS(DIM, MODE) hipLaunchKernelGGL((k_gstencil<T, DIM, MODE>), g, blk, 0, c->s, a, nrhs)
+#define EH_GS(DIM, MODE)                                                                   \
+    if (a.mixed) hipLaunchKernelGGL((k_gstencil<T, DIM, MODE, true>), g, blk, 0, c->s, a, nrhs);  \
+    else hipLaunchKernelGGL((k_gstencil<T, DIM, MODE, false>), g, blk, 0, c->s, a, nrhs)
 #define EH_GS_M(DIM)                        \
     switch (mode) {                         \
         case 0: EH_GS(DIM, 0); break;       \

@@ -210,8 +210,8 @@ def config(k: int, scale: int = 1) -> Workload:
         rec = [(1, ((1 + 2 * r) // scale, 1)) for r in range(256)]
         return Workload("config3_fwi_512", n, h, vp, vs, rho, omega,
                         abc_width=20, abc_sides=abc_all_but_top(2),
-                        sources=src, receivers=rec, levels=4, alpha=0.3,
-                        restart=20)
+                        sources=src, receivers=rec, levels=5, alpha=0.7,
+                        restart=6)
     if k == 4:
         n = (2048 // scale, 2048 // scale)
         vp, vs, rho = layered_medium(n, seed=3, sigma_range=(0.25, 0.49))
