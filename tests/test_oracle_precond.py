@@ -138,3 +138,43 @@ def test_table_2Dlinear_block_acoustic_wcycle():
         res = fgmres(lambda x: H @ x, M, b, restart=5, tol=1e-6, maxit=500)
         assert res.relres_true < 1e-6
         assert abs(res.iters - expect) <= 0.1 * expect, (L, res.iters, expect)
+
+
+def test_tilde_Ap_symmetric_and_equal_to_Ap_for_constant_mu():
+    """The alternative of the Remark after eq. prec, A~_p = B A_f(mu) B^T -
+    w^2 M_p, puts the weighting between divergence and gradient: it is
+    complex symmetric (A_p = B B^T diag(mu) - w^2 M_p is not, for varying mu),
+    and for constant mu the two coincide, boundary cells included."""
+    s = hetero((12, 10), 5)
+    At = s.A_p_tilde().toarray()
+    assert np.abs(At - At.T).max() <= 1e-13 * np.abs(At).max()
+    A = s.A_p().toarray()
+    assert np.abs(A - A.T).max() > 1e-3 * np.abs(A).max()
+    rng = np.random.default_rng(6)
+    shape = (8, 10)
+    rho = rng.uniform(1.0, 2.0, shape)
+    vs = np.sqrt(1.5 / rho)                 # mu = rho vs^2 = 1.5 everywhere
+    vp = vs * rng.uniform(1.8, 2.2, shape)
+    c = ElasticSystem((10, 8), (1.0, 1.1), vp, vs, rho, omega=0.9, abc_width=2,
+                      abc_sides=W.ABC_ALL[2])
+    np.testing.assert_allclose(c.A_p_tilde().toarray(), c.A_p().toarray(), rtol=0, atol=1e-12)
+
+
+def test_tilde_Ap_equivalent_on_smooth_medium():
+    """Remark after eq. prec: on a smooth medium A~_p and A_p give equivalent
+    methods -- with exact block solves, FGMRES needs the same number of
+    iterations (within one) with either distributor and H_p."""
+    n = (32, 32)
+    y = np.linspace(0.0, 1.0, n[1])[:, None] * np.ones((1, n[0]))
+    vp = 2.0 + y
+    vs = 0.5 * vp
+    rho = np.ones_like(vp)
+    om = W.omega_for_ppw(vs, (1.0, 1.0), 10.0)
+    s = ElasticSystem(n, (1.0, 1.0), vp, vs, rho, om, 6, W.abc_all_but_top(2))
+    H = s.H()
+    b = W.point_source_rhs(n, (1.0, 1.0), [(1, (n[0] // 2, 1))])[0]
+    its = []
+    for tilde in (False, True):
+        M = BlockAcoustic(s, alpha=0.0, solver="exact", tilde_Ap=tilde)
+        its.append(fgmres(lambda v: H @ v, M, b, restart=30, tol=1e-6, maxit=200).iters)
+    assert abs(its[0] - its[1]) <= 1, its
