@@ -82,6 +82,9 @@ typedef struct {
                                (down leg) and prolongation + correction + all post-sweeps (up leg);
                                0: one launch per sweep and transfer.  Same arithmetic per point;
                                summation order may differ. */
+    int ap_variant;         /* 0: A_p = B B^T diag(mu) - w^2 M_p (eq. Ap) in the distributor and in
+                               H_p = B B^T + A_p C (eq. Hp), the paper's choice; 1: the alternative of the
+                               Remark after eq. prec, A~_p = B A_f(mu) B^T - w^2 M_p, in both */
 } eh_opts;
 
 typedef struct {

@@ -37,7 +37,7 @@ class EhOpts(ctypes.Structure):
         ("restart", ctypes.c_int), ("abc_width", ctypes.c_int),
         ("abc_sides", ctypes.c_uint), ("gamma0", ctypes.c_double),
         ("intergrid", ctypes.c_int), ("graphs", ctypes.c_int),
-        ("autotune", ctypes.c_int), ("fused", ctypes.c_int),
+        ("autotune", ctypes.c_int), ("fused", ctypes.c_int), ("ap_variant", ctypes.c_int),
     ]
 
 

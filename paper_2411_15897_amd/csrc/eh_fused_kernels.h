@@ -217,7 +217,10 @@ k_fdown(GArgs<T> a, int nrhs) {
     int tx, ty;
     xcd_tile(tx, ty);
 #define EH_FD(FI, KI, WX, WY, NM, MX) down_body<T, FI, KI, WX, WY, NM, MX, CX, CY, NT>(a, slot, lds, nrhs, tx, ty)
-    if (FINE && a.mixed) {
+    if (FINE && kind == 2 && a.tilde) {
+        if (a.mixed) EH_FD(true, 2, 1, 1, 0, true);
+        else EH_FD(true, 2, 1, 1, 0, false);
+    } else if (FINE && a.mixed) {
         if (kind == 2) EH_FD(true, 1, 1, 1, 0, true);
         else if (kind == 0) EH_FD(true, 0, 1, 1, 1, true);
         else EH_FD(true, 0, 1, 1, 2, true);
@@ -371,7 +374,8 @@ k_fup(GArgs<T> a, int nrhs) {
     xcd_tile(tx, ty);
 #define EH_FU(FI, KI, WX, WY, NM) up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT>(a, slot, lds, nrhs, tx, ty)
     if (FINE) {
-        if (kind == 2) EH_FU(true, 1, 1, 1, 0);
+        if (kind == 2 && a.tilde) EH_FU(true, 2, 1, 1, 0);
+        else if (kind == 2) EH_FU(true, 1, 1, 1, 0);
         else if (kind == 0) EH_FU(true, 0, 1, 1, 1);
         else EH_FU(true, 0, 1, 1, 2);
     } else if (a.mixed) {

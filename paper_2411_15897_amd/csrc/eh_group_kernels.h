@@ -43,6 +43,7 @@ struct GArgs {
     T damp;
     T ih[3];                 // 1 / h_a^2
     int mixed;               // mixed intergrid (27-point coarse stencils)
+    int tilde;               // H_p built from A~_p (fine couplings of KIND 2)
 };
 
 #define EH_GROUP_POINT(a, DD)                                                   \

@@ -27,6 +27,10 @@ namespace eh {
 //                (zero on the last point along a).
 //  KIND 1 (H_p): X = B B^T diag(w) - mass: the coupling from p to a
 //                neighbour nb along a is w[nb] / h_a^2.
+//  KIND 2 (H_p built with the Remark's A~_p = B A_f(mu) B^T - w^2 M_p):
+//                the coupling across a face depends on the face and the
+//                neighbour, (1 + mu_f / (lambda+mu)_nb) / h_a^2; wa holds
+//                the pair (to p + e_a, to p - e_a) per point, interleaved.
 template <class T, int KIND, int DIM>
 struct FineCoef {
     T cp[3], cm[3];
@@ -34,7 +38,16 @@ struct FineCoef {
                                          const T* __restrict__ w0, const T* __restrict__ w1,
                                          const T* __restrict__ w2, T ih0, T ih1, T ih2) {
         const int64_t sy = d.g[0], sz = (int64_t)d.g[0] * d.g[1];
-        if (KIND == 0) {
+        if (KIND == 2) {
+            cp[0] = (i + 1 < d.g[0]) ? w0[2 * p] : T(0);
+            cm[0] = (i > 0) ? w0[2 * p + 1] : T(0);
+            cp[1] = (j + 1 < d.g[1]) ? w1[2 * p] : T(0);
+            cm[1] = (j > 0) ? w1[2 * p + 1] : T(0);
+            if (DIM == 3) {
+                cp[2] = (k + 1 < d.g[2]) ? w2[2 * p] : T(0);
+                cm[2] = (k > 0) ? w2[2 * p + 1] : T(0);
+            }
+        } else if (KIND == 0) {
             cp[0] = (i + 1 < d.g[0]) ? w0[p] : T(0);
             cm[0] = (i > 0) ? w0[p - 1] : T(0);
             cp[1] = (j + 1 < d.g[1]) ? w1[p] : T(0);

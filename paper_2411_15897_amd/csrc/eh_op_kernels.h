@@ -83,7 +83,10 @@ k_op_cell(Dims dc, const cplx<Tin>* __restrict__ u0, const cplx<Tin>* __restrict
     }
 }
 
-template <class T, int DIM>
+// TILDE: the Remark's A~_p r = B A_f(mu) B^T r - w^2 rho (1 - i gamma/w) r,
+// sum over faces of mu_f (r_c - r_nb) / h_a^2 with mu_f the mean over the
+// face's existing cells and r = 0 beyond the boundary.
+template <class T, int DIM, bool TILDE>
 __global__ void __launch_bounds__(256)
 k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
              const c128* __restrict__ r2, const c128* __restrict__ rp,
@@ -113,13 +116,24 @@ k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
         if (DIM == 3) div = div + ih2 * (r2[o + f2 + s2] - r2[o + f2]);
         const c128* pr = rp + o;
         const c128 pc = pr[p];
-        // B B^T (mu r): sum_a (2 mu_c r_c - mu_c+ r_c+ - mu_c- r_c-) / h_a^2
         c128 lap = mk(0.0, 0.0);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            c128 s = (2.0 * mup) * pc;
-            if (ci[a] > 0) s = s - mnb[a][0] * pr[p - st[a]];
-            if (ci[a] + 1 < dc.g[a]) s = s - mnb[a][1] * pr[p + st[a]];
+            c128 s;
+            if (TILDE) {
+                // B A_f(mu) B^T r: sum over the two faces along a
+                const bool lo = ci[a] > 0, hi = ci[a] + 1 < dc.g[a];
+                const double mlo = lo ? 0.5 * (mup + mnb[a][0]) : mup;
+                const double mhi = hi ? 0.5 * (mup + mnb[a][1]) : mup;
+                s = (mlo + mhi) * pc;
+                if (lo) s = s - mlo * pr[p - st[a]];
+                if (hi) s = s - mhi * pr[p + st[a]];
+            } else {
+                // B B^T (mu r): sum_a (2 mu_c r_c - mu_c+ r_c+ - mu_c- r_c-) / h_a^2
+                s = (2.0 * mup) * pc;
+                if (ci[a] > 0) s = s - mnb[a][0] * pr[p - st[a]];
+                if (ci[a] + 1 < dc.g[a]) s = s - mnb[a][1] * pr[p + st[a]];
+            }
             lap = lap + ihs[a] * s;
         }
         const c128 Apr = lap - om2 * (mc * pc);

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ehelm.h"
@@ -392,8 +393,41 @@ void upload_cplx(eh_ctx* c, void** dst, const std::vector<std::complex<double>>&
 }
 
 // FP64 stencil (half widths 1) of a fine block for the Galerkin setup.
+// H_p with the Remark's A~_p = B A_f(mu) B^T - w^2 M_p in place of A_p:
+// H~_p = B B^T + A~_p C.  Across the face between cell c and its neighbour
+// nb along axis a the coupling is (1 + mu_f / (lambda+mu)_nb) / h_a^2, mu_f
+// the mean of the face's existing cells (a boundary face has one); the
+// diagonal collects (1 + mu_f / (lambda+mu)_c) / h_a^2 over the cell's
+// faces and the shifted mass / (lambda+mu)_c.  wpm[a] holds the pair
+// (coupling to c + e_a, to c - e_a) per cell.
+void build_Hp_tilde(const eh_ctx* c, const HostMedium& M, double alpha, std::vector<double> wpm[3],
+                    std::vector<std::complex<double>>& D) {
+    const Dims& d = c->dcell;
+    const int64_t nc = c->ncell;
+    const int64_t st[3] = {1, d.g[0], (int64_t)d.g[0] * d.g[1]};
+    for (int a = 0; a < c->dim; ++a) wpm[a].assign(2 * nc, 0.0);
+    D.assign(nc, 0.0);
+    const double om2 = c->omega * c->omega;
+    for (int64_t q = 0; q < nc; ++q) {
+        const int P[3] = {(int)(q % d.g[0]), (int)((q / d.g[0]) % d.g[1]), (int)(q / st[2])};
+        double diag = 0.0;
+        for (int a = 0; a < c->dim; ++a) {
+            const double ih2 = 1.0 / (c->h[a] * c->h[a]);
+            const bool hi = P[a] + 1 < d.g[a], lo = P[a] > 0;
+            const double mhi = hi ? 0.5 * (M.mu[q] + M.mu[q + st[a]]) : M.mu[q];
+            const double mlo = lo ? 0.5 * (M.mu[q] + M.mu[q - st[a]]) : M.mu[q];
+            if (hi) wpm[a][2 * q] = (1.0 + mhi / M.lm[q + st[a]]) * ih2;
+            if (lo) wpm[a][2 * q + 1] = (1.0 + mlo / M.lm[q - st[a]]) * ih2;
+            diag += (2.0 + (mlo + mhi) / M.lm[q]) * ih2;
+        }
+        const std::complex<double> ms = M.rho[q] * std::complex<double>(1.0, -(M.gamma[q] / c->omega + alpha));
+        D[q] = diag - om2 * ms / M.lm[q];
+    }
+}
+
 std::vector<c128> fine_stencil(const eh_ctx* c, const Block& B, const std::vector<double> w[3],
                                const std::vector<std::complex<double>>& D) {
+    const bool tilde = B.kind == c->dim && c->o.ap_variant == 1;
     const Dims& d = B.lev[0].d;
     const int64_t np = d.np();
     Widths wd{{1, 1, c->dim == 3 ? 1 : 0}};
@@ -417,11 +451,13 @@ std::vector<c128> fine_stencil(const eh_ctx* c, const Block& B, const std::vecto
                     e[a] = 1;
                     const double ih2 = 1.0 / (c->h[a] * c->h[a]);
                     if (P[a] + 1 < d.g[a]) {
-                        const double v = (B.kind < c->dim) ? w[a][p] : w[0][p + stride[a]] * ih2;
+                        const double v = tilde ? w[a][2 * p]
+                                               : (B.kind < c->dim) ? w[a][p] : w[0][p + stride[a]] * ih2;
                         put(e[0], e[1], e[2], p, -v);
                     }
                     if (P[a] >= 1) {
-                        const double v = (B.kind < c->dim) ? w[a][p - stride[a]] : w[0][p - stride[a]] * ih2;
+                        const double v = tilde ? w[a][2 * p + 1]
+                                               : (B.kind < c->dim) ? w[a][p - stride[a]] : w[0][p - stride[a]] * ih2;
                         put(-e[0], -e[1], -e[2], p, -v);
                     }
                 }
@@ -574,6 +610,7 @@ GArgs<T> gbase(eh_ctx* c, const int* kinds, int ns, int l, bool coarse_dims_for_
     a.damp = T(c->blk[kinds[0]].lev[l].damp);
     for (int ax = 0; ax < 3; ++ax) a.ih[ax] = T(1.0 / (c->h[ax] * c->h[ax]));
     a.mixed = c->o.intergrid == 1;
+    a.tilde = c->o.ap_variant == 1;
     return a;
 }
 
@@ -585,6 +622,12 @@ dim3 ggrid(const GArgs<T>& a, const dim3& blk) {
         gy = std::max(gy, (int)((a.d[s].g[1] + blk.y - 1) / blk.y));
     }
     return dim3((unsigned)gx, (unsigned)gy, (unsigned)(a.maxg2 * a.ns));
+}
+
+// real couplings stored per fine-level point: d edge weights (A_k), one
+// cell weight (H_p), or a pair per axis (H_p from A~_p)
+inline int fine_couplings(const eh_ctx* c, bool P) {
+    return P ? (c->o.ap_variant == 1 ? 2 * c->dim : 1) : c->dim;
 }
 
 // block group of a launch: 0 for H_p, 1 for the shear blocks
@@ -604,7 +647,7 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
     for (int s = 0; s < a.ns; ++s) {
         const Block& B = c->blk[a.kind[s]];
         const double np = (double)a.d[s].np(), cs = sizeof(cplx<T>), rs = sizeof(T);
-        double coefb = l == 0 ? np * (cs + (P ? 1 : c->dim) * rs) : np * B.lev[l].w.nst() * cs;
+        double coefb = l == 0 ? np * (cs + fine_couplings(c, P) * rs) : np * B.lev[l].w.nst() * cs;
         double vecb = (mode == 0 || mode == 3) ? 2 * np * cs : (mode == 4 ? 3 * np * cs : 3 * np * cs);
         if (mode == 0) coefb = np * cs;
         by += coefb + nrhs * vecb;
@@ -624,8 +667,11 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
         case 3: EH_GF(KIND, DIM, 3); break;     \
         default: EH_GF(KIND, DIM, 4); break;    \
     }
-        if (c->dim == 2) { if (P) { EH_GF_M(1, 2) } else { EH_GF_M(0, 2) } }
-        else { if (P) { EH_GF_M(1, 3) } else { EH_GF_M(0, 3) } }
+        if (c->dim == 2) {
+            if (P && a.tilde) { EH_GF_M(2, 2) } else if (P) { EH_GF_M(1, 2) } else { EH_GF_M(0, 2) }
+        } else {
+            if (P && a.tilde) { EH_GF_M(2, 3) } else if (P) { EH_GF_M(1, 3) } else { EH_GF_M(0, 3) }
+        }
 #undef EH_GF_M
 #undef EH_GF
     } else {
@@ -740,7 +786,7 @@ void fused_level(eh_ctx* c, const int* kinds, int ns, int l, const void* const* 
         const Level& Lv = B.lev[l];
         const Level& Cv = B.lev[l + 1];
         const double np = (double)Lv.d.np(), npc = (double)Cv.d.np();
-        cbytes += l == 0 ? np * (cs + (P ? 1 : c->dim) * rs) : np * (Lv.w.nst() + 1) * cs;
+        cbytes += l == 0 ? np * (cs + fine_couplings(c, P) * rs) : np * (Lv.w.nst() + 1) * cs;
         vdown += (np + npc) * cs;
         vup += (2 * np + npc) * cs;
         cf[s] = Cv.f; ce[s] = Cv.e; vcv[s] = Cv.d.np();
@@ -953,9 +999,9 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
 
 std::string tune_signature(const eh_ctx* c, int nrhs) {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "d%d n%lldx%lldx%lld L%d p%d i%d r%d f%d n%d", c->dim, (long long)c->n[0],
-                  (long long)c->n[1], (long long)c->n[2], c->o.levels, c->o.mg_precision, c->o.intergrid, nrhs,
-                  c->o.fused, c->o.nu_post);
+    std::snprintf(buf, sizeof(buf), "d%d n%lldx%lldx%lld L%d p%d i%d r%d f%d n%d a%d", c->dim,
+                  (long long)c->n[0], (long long)c->n[1], (long long)c->n[2], c->o.levels, c->o.mg_precision,
+                  c->o.intergrid, nrhs, c->o.fused, c->o.nu_post, c->o.ap_variant);
     return buf;
 }
 
@@ -1221,16 +1267,21 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
     const c128* r2 = d == 3 ? r + c->off[2] : r;
     {
     Timed tm(c, KC_DISTRIBUTE, 24.0 * c->ncell + (double)nrhs * (c->ndof * 16.0 + c->ncell * sizeof(cplx<T>)));
-    if (d == 2)
-        hipLaunchKernelGGL((k_distribute<T, 2>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, r + c->off[0],
-                           r + c->off[1], r2, r + c->off[d], c->mu, c->mcell, c->omega * c->omega,
-                           1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell, rs,
-                           rss);
-    else
-        hipLaunchKernelGGL((k_distribute<T, 3>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, r + c->off[0],
-                           r + c->off[1], r2, r + c->off[d], c->mu, c->mcell, c->omega * c->omega,
-                           1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f, nrhs, vr, c->ncell, rs,
-                           rss);
+    auto launch = [&](auto tilde_tag) {
+        constexpr bool TILDE = decltype(tilde_tag)::value;
+        if (d == 2)
+            hipLaunchKernelGGL((k_distribute<T, 2, TILDE>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell,
+                               r + c->off[0], r + c->off[1], r2, r + c->off[d], c->mu, c->mcell,
+                               c->omega * c->omega, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f,
+                               nrhs, vr, c->ncell, rs, rss);
+        else
+            hipLaunchKernelGGL((k_distribute<T, 3, TILDE>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell,
+                               r + c->off[0], r + c->off[1], r2, r + c->off[d], c->mu, c->mcell,
+                               c->omega * c->omega, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f,
+                               nrhs, vr, c->ncell, rs, rss);
+    };
+    if (c->o.ap_variant == 1) launch(std::true_type{});
+    else launch(std::false_type{});
     HIPCHK(hipGetLastError());
     }
     cplx<T>* Z = (cplx<T>*)z;
@@ -1572,6 +1623,7 @@ void eh_default_opts(eh_opts* o) {
     o->graphs = 1;
     o->autotune = 1;
     o->fused = 1;
+    o->ap_variant = 0;
 }
 
 const char* eh_last_error(const eh_ctx* c) {
@@ -1608,6 +1660,7 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
     if (o.graphs != 0 && o.graphs != 1) { g_create_error = "graphs must be 0 or 1"; return EH_ERR_ARG; }
     if (o.autotune != 0 && o.autotune != 1) { g_create_error = "autotune must be 0 or 1"; return EH_ERR_ARG; }
     if (o.fused != 0 && o.fused != 1) { g_create_error = "fused must be 0 or 1"; return EH_ERR_ARG; }
+    if (o.ap_variant != 0 && o.ap_variant != 1) { g_create_error = "ap_variant must be 0 or 1"; return EH_ERR_ARG; }
     if (!(o.alpha >= 0.0) || !std::isfinite(o.alpha)) { g_create_error = "alpha must be >= 0"; return EH_ERR_ARG; }
     int64_t ncell = 1;
     for (int a = 0; a < dim; ++a) {
@@ -1701,6 +1754,12 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
                 build_Ak(c, M, b, 0.0, w0, D0);
                 for (int a = 0; a < dim; ++a) upload_real<double>(c, (void**)&c->k1w[b][a], w0[a]);
                 upload_cplx<double>(c, (void**)&c->k1D[b], D0);
+                for (int a = 0; a < dim; ++a) {
+                    if (f32) upload_real<float>(c, &B.fw[a], w[a]);
+                    else upload_real<double>(c, &B.fw[a], w[a]);
+                }
+            } else if (o.ap_variant == 1) {
+                build_Hp_tilde(c, M, o.alpha, w, D);
                 for (int a = 0; a < dim; ++a) {
                     if (f32) upload_real<float>(c, &B.fw[a], w[a]);
                     else upload_real<double>(c, &B.fw[a], w[a]);

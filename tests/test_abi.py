@@ -35,7 +35,7 @@ def test_default_opts():
     assert list(o.damping[:3]) == [0.8, 0.8, 0.3]
     assert o.mg_precision == 32 and o.restart == 20 and o.abc_width == 20
     assert o.gamma0 == pytest.approx(0.01 * math.pi)
-    assert (o.intergrid, o.graphs, o.autotune, o.fused) == (0, 1, 1, 1)
+    assert (o.intergrid, o.graphs, o.autotune, o.fused, o.ap_variant) == (0, 1, 1, 1, 0)
 
 
 def _create(n, vp, vs, rho, omega=1.0, levels=2, dim=None, **kw):

@@ -437,3 +437,36 @@ def test_fused_legs_match_oracle_and_unfused(n, levels, nu2, intergrid):
         assert rel(z5[k], zu[k]) <= 1e-12
     for g in (g64, u64, g32, u32):
         g.close()
+
+
+@pytest.mark.parametrize("n,levels", [((48, 40), 3), ((8, 8, 8), 2)])
+def test_tilde_Ap_variant_parity(n, levels):
+    """The Remark's A~_p in the distributor and in H~_p = B B^T + A~_p C:
+    the H~_p block on every level (FP64, 1e-12), its V-cycle with the fused
+    legs and with the per-sweep kernels (1e-10), and the whole
+    preconditioner against the oracle's (FP64, 1e-10)."""
+    say("tilde A_p parity", n, levels)
+    alpha = 0.3
+    d = len(n)
+    nu = (1, 2) if d == 2 else (2, 2)
+    damping = (0.8, 0.8, 0.3) if d == 2 else (0.8, 0.8, 0.2)
+    kw = dict(levels=levels, alpha=alpha, mg_precision=64, nu=nu, damping=damping, ap_variant="tilde")
+    g, s = make(n, seed=21, **kw)
+    u, _ = make(n, seed=21, fused=False, **kw)
+    Hp = (s.BBt() + s.A_p_tilde(alpha) @ s.C).tocsr()
+    mg = Hierarchy(Hp, s.n, (False,) * d, levels, damping=damping, nu=nu)
+    for l in range(levels):
+        x = crand(mg.ops[l].shape[0], 70 + l)
+        y = g.block_apply(d, l, to_dev(x)).cpu().numpy()
+        assert rel(y, mg.ops[l] @ x) <= 1e-12, l
+    f = crand(Hp.shape[0], 80)
+    e = g.block_cycle(d, to_dev(f)).cpu().numpy()
+    assert rel(e, mg(f)) <= 1e-10
+    assert rel(u.block_cycle(d, to_dev(f)).cpu().numpy(), e) <= 1e-12
+    M = BlockAcoustic(s, alpha=alpha, solver="mg", levels=levels, cycle="V", nu=nu, damping=damping,
+                      tilde_Ap=True)
+    r = crand((2, s.ndof), 81)
+    z = g.apply_preconditioner(to_dev(r)).cpu().numpy()
+    for k in range(2):
+        assert rel(z[k], M.apply(r[k])) <= 1e-10
+    g.close(); u.close()
