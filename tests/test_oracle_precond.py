@@ -178,3 +178,33 @@ def test_tilde_Ap_equivalent_on_smooth_medium():
         M = BlockAcoustic(s, alpha=0.0, solver="exact", tilde_Ap=tilde)
         its.append(fgmres(lambda v: H @ v, M, b, restart=30, tol=1e-6, maxit=200).iters)
     assert abs(its[0] - its[1]) <= 1, its
+
+
+def test_power_method_matches_dense_spectral_radius():
+    """The matrix-free power method on Z(alpha) (LU solves for the shifted
+    blocks) converges to the spectral radius of the dense Z(alpha) on a tiny
+    heterogeneous grid; alpha = 0 is eq. Z of Theorem 3.1."""
+    from oracle.analysis import ZOperator, power_method
+    s = hetero((10, 8), 7, omega=1.0)
+    rng = np.random.default_rng(8)
+    v0 = rng.standard_normal(s.ncell) + 1j * rng.standard_normal(s.ncell)
+    for alpha in (0.0, 0.3):
+        rho = np.abs(np.linalg.eigvals(Z_matrix(s, alpha))).max()
+        op = ZOperator(s, alpha)
+        v = rng.standard_normal(s.ncell) + 1j * rng.standard_normal(s.ncell)
+        np.testing.assert_allclose(op(v), Z_matrix(s, alpha) @ v, rtol=1e-10, atol=1e-12 * np.linalg.norm(v))
+        est = power_method(op, v0, 300)
+        assert abs(est[-1] - rho) <= 2e-3 * rho, (alpha, est[-1], rho)
+
+
+def test_Z_vanishes_for_constant_media_and_shrinks_with_the_shift():
+    """Constant media: Xi = 0, so Z = 0 (one-iteration convergence).  On a
+    heterogeneous grid the spectral radius of Z(alpha) decreases as the
+    shift grows (Section 5, the rho(Z) curves)."""
+    n = (10, 8)
+    vp, vs, rho = W.constant_medium(n, 2.0, 1.0, 1.0)
+    c = ElasticSystem(n, (1.0, 1.0), vp, vs, rho, omega=1.0, abc_width=0, abc_sides=0)
+    assert np.abs(Z_matrix(c)).max() <= 1e-10
+    s = hetero((12, 10), 9, omega=1.5)
+    radii = [np.abs(np.linalg.eigvals(Z_matrix(s, a))).max() for a in (0.0, 0.2, 0.5, 1.0)]
+    assert all(b < a for a, b in zip(radii, radii[1:])), radii
