@@ -153,6 +153,33 @@ eh_status eh_block_dims(const eh_ctx *ctx, int block, int level, int64_t *out);
 eh_status eh_solve(eh_ctx *ctx, const void *b, void *x, int nrhs, double tol,
                    int maxit, eh_info *info);
 
+/* Solve one shifted acoustic block alone, X_b x = f on the fine grid
+ * (block 0..dim-1: A_{b+1}, block dim: H_p; the operators the
+ * preconditioner inverts, eq. shift), with FGMRES(restart) right-
+ * preconditioned by the block's multigrid cycle.  The operator is applied
+ * in the multigrid precision.  f, x: complex128 device buffers of
+ * nrhs * (points of the block) entries; info as for eh_solve.
+ * Synchronises.  Returns EH_NOT_CONVERGED if any right-hand side missed
+ * tol. */
+eh_status eh_block_solve(eh_ctx *ctx, int block, const void *f, void *x, int nrhs,
+                         double tol, int maxit, eh_info *info);
+
+/* y = Z(alpha) v for one cell vector: Z = Xi A^-1 B^T H_p^-1 (eq. Z,
+ * Theorem 3.1) with the commutator Xi = B A - A_p B (eq. commutator;
+ * B A - A~_p B when ap_variant = 1) and the inverses of the shifted
+ * blocks the preconditioner uses (alpha = 0 gives eq. Z exactly).  Each
+ * inverse is an eh_block_solve to tol (at most maxit iterations).  v, y:
+ * complex128 device buffers of n_cells entries.  Synchronises; returns
+ * EH_NOT_CONVERGED if an inner solve missed tol. */
+eh_status eh_apply_Z(eh_ctx *ctx, const void *v, void *y, double tol, int maxit);
+
+/* Power method for the spectral radius of Z(alpha) (Section 5, rho(Z) as a
+ * function of the shift): v <- Z v / ||Z v||, starting from the caller's
+ * v (device, n_cells complex128, normalised first, overwritten by the last
+ * iterate); est[k] = ||Z v_k|| for k < iters (host array).  Inner solves as
+ * eh_apply_Z.  Synchronises. */
+eh_status eh_power_Z(eh_ctx *ctx, void *v, int iters, double tol, int maxit, double *est);
+
 /* Gradient of Phi = 1/2 sum_s ||P_r u_s - d_s||^2 with respect to per-cell
  * vp, vs and rho: g_m = -Re sum_s lam_s^H (dH/dm) u_s, with dH/dm from the
  * assembly of eq. mixed-discretized (mu through the cell and edge averages,

@@ -19,6 +19,7 @@ EXPORTED = [
     "eh_apply_preconditioner", "eh_block_cycle", "eh_block_apply",
     "eh_block_dims", "eh_solve", "eh_gradient", "eh_misfit", "eh_set_stream",
     "eh_destroy", "eh_last_error", "eh_timer_enable", "eh_timer_read",
+    "eh_block_solve", "eh_apply_Z", "eh_power_Z",
 ]
 
 KERNEL_CLASSES = {
@@ -77,6 +78,12 @@ def lib():
     L.eh_block_dims.restype = i32
     L.eh_solve.argtypes = [vp, vp, vp, i32, dbl, i32, P(EhInfo)]
     L.eh_solve.restype = i32
+    L.eh_block_solve.argtypes = [vp, i32, vp, vp, i32, dbl, i32, P(EhInfo)]
+    L.eh_block_solve.restype = i32
+    L.eh_apply_Z.argtypes = [vp, vp, vp, dbl, i32]
+    L.eh_apply_Z.restype = i32
+    L.eh_power_Z.argtypes = [vp, vp, i32, dbl, i32, P(dbl)]
+    L.eh_power_Z.restype = i32
     L.eh_gradient.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.eh_gradient.restype = i32
     L.eh_misfit.argtypes = [vp, vp, vp, i32, vp, i32, vp, P(dbl)]

@@ -143,6 +143,19 @@ k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
     }
 }
 
+// out[q * vo + i] = s_q in[q * vi + i] in the output precision, s_q =
+// rs[q * rss] (1 without rs); one grid row per right-hand side
+template <class To>
+__global__ void __launch_bounds__(256)
+k_cast_scaled(int64_t n, const c128* __restrict__ in, int64_t vi, const double* __restrict__ rs, int64_t rss,
+              cplx<To>* __restrict__ out, int64_t vo) {
+    const int q = blockIdx.y;
+    const double sq = rs ? rs[q * rss] : 1.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[q * vo + i] = ccast<To>(sq * in[q * vi + i]);
+}
+
 template <class To, class Ti>
 __global__ void __launch_bounds__(256)
 k_cast(int64_t n, const cplx<Ti>* __restrict__ in, cplx<To>* __restrict__ out) {

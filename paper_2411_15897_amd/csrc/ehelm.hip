@@ -157,6 +157,8 @@ struct eh_ctx {
     ArnStatus* arn_dev = nullptr;     // the same memory as the device sees it
     std::vector<hipEvent_t> arn_ev;
     void* tmpT = nullptr;         // nrhs * ndof multigrid precision (preconditioner I/O)
+    c128* zbuf = nullptr;         // 2 * ndof: work vectors of the Z(alpha) mat-vec
+    c128* zy = nullptr;           // ncell: Z v in the power method
     int64_t tmpT_elems = 0;
     std::vector<void*> allocs;
     std::string err;
@@ -1406,12 +1408,12 @@ void ensure_krylov(eh_ctx* c, int nrhs, int m) {
 // Gram-Schmidt pass over columns [0, m): MODE as in k_gs.  coef/out are
 // device arrays [nrhs][m] (out: [nrhs][1] for norms).
 template <int MODE>
-void gs_pass(eh_ctx* c, int m, int nrhs, const c128* V, const c128* w, const c128* coef, c128* out,
+void gs_pass(eh_ctx* c, int64_t n, int m, int nrhs, const c128* V, const c128* w, const c128* coef, c128* out,
              c128* wout = nullptr) {
-    const int nblk = c->kry_nblk;
+    const int nblk = (int)std::max<int64_t>(1, (n + KRY_E * KRY_THREADS - 1) / (KRY_E * KRY_THREADS));
     const double vecs = (MODE == 0 || MODE == 4) ? m + 1 : (MODE == 3 ? 1 : m + 2);
-    Timed tm(c, KC_KRYLOV, vecs * nrhs * c->ndof * sizeof(c128));
-    hipLaunchKernelGGL((k_gs<MODE>), dim3(nblk, nrhs), dim3(KRY_THREADS), 0, c->s, c->ndof, m, nrhs, V, w,
+    Timed tm(c, KC_KRYLOV, vecs * nrhs * n * sizeof(c128));
+    hipLaunchKernelGGL((k_gs<MODE>), dim3(nblk, nrhs), dim3(KRY_THREADS), 0, c->s, n, m, nrhs, V, w,
                        coef, c->partial, wout);
     HIPCHK(hipGetLastError());
     const int mm = (MODE == 0 || MODE == 1) ? m : (MODE == 4 ? 2 * m : 1);
@@ -1427,13 +1429,17 @@ void gs_pass(eh_ctx* c, int m, int nrhs, const c128* V, const c128* w, const c12
 // at most one step is queued beyond convergence (it then acts on inactive
 // right-hand sides only: scale 0, no column counted).  A cycle start
 // computes r = b - H x in FP64, so the last start gives the true residual.
-template <class T>
-eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, int maxit, eh_info* info) {
+//
+// The problem enters through three callbacks, each enqueueing on c->s:
+//   op_x(x, W)        W = X x for an FP64 vector (cycle starts)
+//   op_z(z_j, W)      W = X z_j for a preconditioned vector (multigrid precision)
+//   prec(v, sv, z_j)  z_j = M (sv[q * (m+1)] v) per right-hand side q
+// with vectors of length n, right-hand side q at offset q * n.  Graph
+// capture is used only for the full system (`graphs`).
+template <class T, class OpX, class OpZ, class Prec>
+eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool graphs, const c128* b, c128* x,
+                      int nrhs, double tol, int maxit, eh_info* info) {
     const int m = c->o.restart;
-    ensure_krylov(c, nrhs, m);
-    ensure_mg_workspace(c, nrhs);     // no allocation may happen inside a graph capture
-    maybe_autotune<T>(c, nrhs);
-    const int64_t n = c->ndof;
     const int64_t vstep = (int64_t)nrhs * n;    // distance between basis vectors
     cplx<T>* Z = (cplx<T>*)c->Z;
     ArnState S = c->arn;
@@ -1464,11 +1470,11 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
         if (first) {
             HIPCHK(hipMemcpyAsync(c->V, b, (size_t)vstep * sizeof(c128), hipMemcpyDeviceToDevice, c->s));
         } else {
-            apply_H<double>(c, x, n, c->W, n, nrhs);
+            op_x(x, c->W);
             hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, b, c->W, c->V);
             HIPCHK(hipGetLastError());
         }
-        gs_pass<3>(c, 1, nrhs, nullptr, c->V, nullptr, d3);
+        gs_pass<3>(c, n, 1, nrhs, nullptr, c->V, nullptr, d3);
         hipLaunchKernelGGL(k_arn_start, dim3(rgrid), dim3(64), 0, c->s, S, (const c128*)d3, first ? 1 : 0, tol,
                            ds + (size_t)m * nrhs);
         HIPCHK(hipGetLastError());
@@ -1481,17 +1487,17 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
             c128* Vj = c->V + (int64_t)j * vstep;
             cplx<T>* Zj = Z + (int64_t)j * vstep;
             auto body = [&]() {
-                apply_M<T>(c, Vj, n, Zj, n, nrhs, S.sv + j, m + 1);
-                apply_H<T>(c, Zj, n, c->W, n, nrhs);
-                gs_pass<4>(c, j + 1, nrhs, c->V, c->W, nullptr, d1);
+                prec(Vj, S.sv + j, Zj);
+                op_z(Zj, c->W);
+                gs_pass<4>(c, n, j + 1, nrhs, c->V, c->W, nullptr, d1);
                 hipLaunchKernelGGL(k_arn_coef, dim3(nrhs), dim3(64), 0, c->s, S, j, (const c128*)d1, d2);
                 HIPCHK(hipGetLastError());
-                gs_pass<2>(c, j + 1, nrhs, c->V, c->W, d2, d3, Vj + vstep);
+                gs_pass<2>(c, n, j + 1, nrhs, c->V, c->W, d2, d3, Vj + vstep);
                 hipLaunchKernelGGL(k_arn_givens, dim3(rgrid), dim3(64), 0, c->s, S, j, (const c128*)d3,
                                    ds + (size_t)j * nrhs);
                 HIPCHK(hipGetLastError());
             };
-            if (c->o.graphs && c->timer_mask == 0) {
+            if (graphs && c->timer_mask == 0) {
                 if (c->graph_nrhs != nrhs || (int)c->graphs.size() != m) {
                     drop_graphs(c);
                     c->graphs.resize(m);
@@ -1566,6 +1572,158 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
         }
     }
     return all ? EH_OK : EH_NOT_CONVERGED;
+}
+
+// The full system: H x = b with the block-acoustic preconditioner.
+template <class T>
+eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, int maxit, eh_info* info) {
+    ensure_krylov(c, nrhs, c->o.restart);
+    ensure_mg_workspace(c, nrhs);     // no allocation may happen inside a graph capture
+    maybe_autotune<T>(c, nrhs);
+    const int64_t n = c->ndof;
+    const int m = c->o.restart;
+    auto op_x = [&](const c128* xx, c128* w) { apply_H<double>(c, xx, n, w, n, nrhs); };
+    auto op_z = [&](const cplx<T>* z, c128* w) { apply_H<T>(c, z, n, w, n, nrhs); };
+    auto prec = [&](const c128* v, const double* sv, cplx<T>* z) { apply_M<T>(c, v, n, z, n, nrhs, sv, m + 1); };
+    return fgmres_core<T>(c, n, op_x, op_z, prec, c->o.graphs != 0, b, x, nrhs, tol, maxit, info);
+}
+
+eh_status fail(eh_ctx* c, eh_status st, const std::string& msg);
+
+// One acoustic block alone: X_b x = f on the fine grid with FGMRES, right-
+// preconditioned by the block's multigrid cycle (the shifted operator of
+// the block, as inverted inside the preconditioner).  The operator is
+// applied in the multigrid precision.
+template <class T>
+eh_status block_solve_impl(eh_ctx* c, int block, const c128* f, c128* x, int nrhs, double tol, int maxit,
+                           eh_info* info) {
+    ensure_krylov(c, nrhs, c->o.restart);
+    ensure_mg_workspace(c, nrhs);
+    maybe_autotune<T>(c, nrhs);
+    Level& L = c->blk[block].lev[0];
+    const int64_t n = L.d.np();
+    const int m = c->o.restart;
+    const int kinds[1] = {block};
+    auto apply_T = [&](const cplx<T>* u, int64_t vu, c128* w) {
+        GArgs<T> a = gbase<T>(c, kinds, 1, 0, false);
+        a.u[0] = u;
+        a.vu[0] = vu;
+        a.out[0] = (cplx<T>*)L.t;
+        a.vo[0] = n;
+        gsweep<T>(c, a, 0, 3, nrhs);
+        hipLaunchKernelGGL((k_cast<double, T>), dim3(lin_grid(n * nrhs, 256, 8192)), dim3(256), 0, c->s,
+                           n * nrhs, (const cplx<T>*)L.t, w);
+        HIPCHK(hipGetLastError());
+    };
+    auto op_x = [&](const c128* xx, c128* w) {
+        hipLaunchKernelGGL((k_cast_scaled<T>), dim3(lin_grid(n, 256, 4096), nrhs), dim3(256), 0, c->s, n, xx, n,
+                           (const double*)nullptr, (int64_t)0, (cplx<T>*)L.u, n);
+        HIPCHK(hipGetLastError());
+        apply_T((const cplx<T>*)L.u, n, w);
+    };
+    auto op_z = [&](const cplx<T>* z, c128* w) { apply_T(z, n, w); };
+    auto prec = [&](const c128* v, const double* sv, cplx<T>* z) {
+        hipLaunchKernelGGL((k_cast_scaled<T>), dim3(lin_grid(n, 256, 4096), nrhs), dim3(256), 0, c->s, n, v, n,
+                           sv, (int64_t)(m + 1), (cplx<T>*)L.f, n);
+        HIPCHK(hipGetLastError());
+        const void* fa[1] = {L.f};
+        const int64_t vf[1] = {n};
+        void* out[1] = {z};
+        gcycle<T>(c, kinds, 1, 0, fa, vf, out, vf, false, nrhs);
+    };
+    return fgmres_core<T>(c, n, op_x, op_z, prec, false, f, x, nrhs, tol, maxit, info);
+}
+
+void ensure_zbuf(eh_ctx* c) {
+    if (c->zbuf) return;
+    c->zbuf = c->alloc<c128>((size_t)2 * c->ndof);
+    c->zy = c->alloc<c128>((size_t)c->ncell);
+}
+
+// y = Z(alpha) v = Xi A_alpha^-1 B^T H_p,alpha^-1 v for one cell vector
+// (eq. Z with the preconditioner's shifted blocks; Xi = B A - A_p B, or
+// B A - A~_p B with the Remark's variant).  The inverses are block solves
+// to `tol`; with w = A_alpha^-1 B^T t, Xi w is the distributor applied to
+// H [w; 0] = [A w; B w].
+template <class T>
+eh_status apply_Z_impl(eh_ctx* c, const c128* v, c128* y, double tol, int maxit) {
+    ensure_zbuf(c);
+    const int d = c->dim;
+    c128* z1 = c->zbuf;
+    c128* z2 = c->zbuf + c->ndof;
+    eh_info inf{};
+    hipLaunchKernelGGL((k_fill<c128>), dim3(lin_grid(c->ndof, 256, 4096)), dim3(256), 0, c->s, c->ndof, z1,
+                       mk(0.0, 0.0));
+    HIPCHK(hipGetLastError());
+    eh_status st = block_solve_impl<T>(c, d, v, z1 + c->off[d], 1, tol, maxit, &inf);
+    if (st != EH_OK) return st == EH_NOT_CONVERGED ? fail(c, st, "inner H_p solve did not converge") : st;
+    apply_H<double>(c, z1, c->ndof, z2, c->ndof, 1);            // u rows: B^T t
+    for (int k = 0; k < d; ++k) {
+        st = block_solve_impl<T>(c, k, z2 + c->off[k], z1 + c->off[k], 1, tol, maxit, &inf);
+        if (st != EH_OK) return st == EH_NOT_CONVERGED ? fail(c, st, "inner A_k solve did not converge") : st;
+    }
+    hipLaunchKernelGGL((k_fill<c128>), dim3(lin_grid(c->ncell, 256, 4096)), dim3(256), 0, c->s, c->ncell,
+                       z1 + c->off[d], mk(0.0, 0.0));
+    HIPCHK(hipGetLastError());
+    apply_H<double>(c, z1, c->ndof, z2, c->ndof, 1);            // [A w; B w]
+    const c128* r2 = d == 3 ? z2 + c->off[2] : z2;
+    auto launch = [&](auto tilde_tag) {
+        constexpr bool TILDE = decltype(tilde_tag)::value;
+        if (d == 2)
+            hipLaunchKernelGGL((k_distribute<double, 2, TILDE>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell,
+                               z2 + c->off[0], z2 + c->off[1], r2, z2 + c->off[d], c->mu, c->mcell,
+                               c->omega * c->omega, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], y, 1, c->ndof,
+                               c->ncell, (const double*)nullptr, (int64_t)0);
+        else
+            hipLaunchKernelGGL((k_distribute<double, 3, TILDE>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell,
+                               z2 + c->off[0], z2 + c->off[1], r2, z2 + c->off[d], c->mu, c->mcell,
+                               c->omega * c->omega, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], y, 1, c->ndof,
+                               c->ncell, (const double*)nullptr, (int64_t)0);
+    };
+    if (c->o.ap_variant == 1) launch(std::true_type{});
+    else launch(std::false_type{});
+    HIPCHK(hipGetLastError());
+    return EH_OK;
+}
+
+// ||w||_2 of one vector of length n (deterministic reduction), synchronising
+double norm2(eh_ctx* c, const c128* w, int64_t n) {
+    c128* d = c->dsmall;
+    gs_pass<3>(c, n, 1, 1, nullptr, w, nullptr, d);
+    c128 h;
+    HIPCHK(hipMemcpyAsync(&h, d, sizeof(c128), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    return std::sqrt(std::max(0.0, h.re));
+}
+
+// Power method on Z(alpha) (Section 5: rho(Z) as a function of the shift):
+// v <- Z v / ||Z v|| from the caller's v (normalised first), est[k] =
+// ||Z v_k||.  v holds the last iterate on return.
+template <class T>
+eh_status power_Z_impl(eh_ctx* c, c128* v, int iters, double tol, int maxit, double* est) {
+    ensure_krylov(c, 1, c->o.restart);
+    ensure_zbuf(c);
+    const int64_t nc = c->ncell;
+    const double nv = norm2(c, v, nc);
+    if (!(nv > 0.0) || !std::isfinite(nv)) return fail(c, EH_ERR_ARG, "power method start vector is zero or not finite");
+    hipLaunchKernelGGL(k_scal, dim3(lin_grid(nc, 256, 4096)), dim3(256), 0, c->s, nc, 1.0 / nv, v, v);
+    HIPCHK(hipGetLastError());
+    for (int k = 0; k < iters; ++k) {
+        eh_status st = apply_Z_impl<T>(c, v, c->zy, tol, maxit);
+        if (st != EH_OK) return st;
+        const double ny = norm2(c, c->zy, nc);
+        est[k] = ny;
+        if (!std::isfinite(ny)) return fail(c, EH_ERR_STATE, "non-finite value in the power method");
+        if (ny == 0.0) {
+            for (int q = k + 1; q < iters; ++q) est[q] = 0.0;
+            break;
+        }
+        hipLaunchKernelGGL(k_scal, dim3(lin_grid(nc, 256, 4096)), dim3(256), 0, c->s, nc, 1.0 / ny,
+                           (const c128*)c->zy, v);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(c->s));
+    return EH_OK;
 }
 
 eh_status fail(eh_ctx* c, eh_status st, const std::string& msg) {
@@ -1975,6 +2133,59 @@ eh_status eh_solve(eh_ctx* c, const void* b, void* x, int nrhs, double tol, int 
         return fail(c, EH_ERR_STATE, e.msg);
     } catch (const HipError& e) {
         c->s = user;
+        return from_hip(c, e);
+    }
+}
+
+eh_status eh_block_solve(eh_ctx* c, int block, const void* f, void* x, int nrhs, double tol, int maxit,
+                         eh_info* info) {
+    EH_GUARD(c)
+    if (block < 0 || block > c->dim || !f || !x || nrhs < 1 || !(tol > 0.0) || maxit < 0)
+        return fail(c, EH_ERR_ARG, "invalid block solve arguments");
+    try {
+        eh_status st;
+        if (c->o.mg_precision == 64) st = block_solve_impl<double>(c, block, (const c128*)f, (c128*)x, nrhs, tol, maxit, info);
+        else st = block_solve_impl<float>(c, block, (const c128*)f, (c128*)x, nrhs, tol, maxit, info);
+        HIPCHK(hipStreamSynchronize(c->s));
+        return st;
+    } catch (const StateError& e) {
+        const hipError_t se = hipStreamSynchronize(c->s);
+        if (se != hipSuccess) return from_hip(c, HipError{se, "hipStreamSynchronize"});
+        return fail(c, EH_ERR_STATE, e.msg);
+    } catch (const HipError& e) {
+        return from_hip(c, e);
+    }
+}
+
+eh_status eh_apply_Z(eh_ctx* c, const void* v, void* y, double tol, int maxit) {
+    EH_GUARD(c)
+    if (!v || !y || !(tol > 0.0) || maxit < 1) return fail(c, EH_ERR_ARG, "invalid Z arguments");
+    try {
+        eh_status st;
+        if (c->o.mg_precision == 64) st = apply_Z_impl<double>(c, (const c128*)v, (c128*)y, tol, maxit);
+        else st = apply_Z_impl<float>(c, (const c128*)v, (c128*)y, tol, maxit);
+        HIPCHK(hipStreamSynchronize(c->s));
+        return st;
+    } catch (const StateError& e) {
+        const hipError_t se = hipStreamSynchronize(c->s);
+        if (se != hipSuccess) return from_hip(c, HipError{se, "hipStreamSynchronize"});
+        return fail(c, EH_ERR_STATE, e.msg);
+    } catch (const HipError& e) {
+        return from_hip(c, e);
+    }
+}
+
+eh_status eh_power_Z(eh_ctx* c, void* v, int iters, double tol, int maxit, double* est) {
+    EH_GUARD(c)
+    if (!v || iters < 1 || !est || !(tol > 0.0) || maxit < 1) return fail(c, EH_ERR_ARG, "invalid power method arguments");
+    try {
+        if (c->o.mg_precision == 64) return power_Z_impl<double>(c, (c128*)v, iters, tol, maxit, est);
+        return power_Z_impl<float>(c, (c128*)v, iters, tol, maxit, est);
+    } catch (const StateError& e) {
+        const hipError_t se = hipStreamSynchronize(c->s);
+        if (se != hipSuccess) return from_hip(c, HipError{se, "hipStreamSynchronize"});
+        return fail(c, EH_ERR_STATE, e.msg);
+    } catch (const HipError& e) {
         return from_hip(c, e);
     }
 }

@@ -185,6 +185,37 @@ class ElasticHelmholtz:
         return x, [dict(iters=i.iters, converged=bool(i.converged), relres_true=i.relres_true,
                         relres_est=i.relres_est) for i in info]
 
+    def block_solve(self, block, f, tol=1e-10, maxit=1000):
+        """Solve one shifted acoustic block alone (eh_block_solve)."""
+        np_ = int(np.prod(self.block_dims(block, 0)))
+        nrhs = self._nrhs(f, np_)
+        _check_dev(f, torch.complex128, nrhs * np_, "f")
+        x = torch.empty_like(f)
+        info = (N.EhInfo * nrhs)()
+        self._check(self._lib.eh_block_solve(self._ctx, int(block), _ptr(f), _ptr(x), nrhs, float(tol),
+                                             int(maxit), info))
+        return x, [dict(iters=i.iters, converged=bool(i.converged), relres_true=i.relres_true) for i in info]
+
+    def apply_Z(self, v, tol=1e-10, maxit=1000):
+        """y = Z(alpha) v for one cell vector (eh_apply_Z)."""
+        _check_dev(v, torch.complex128, self.ncell, "v")
+        y = torch.empty_like(v)
+        st = self._check(self._lib.eh_apply_Z(self._ctx, _ptr(v), _ptr(y), float(tol), int(maxit)))
+        if st == N.EH_NOT_CONVERGED:
+            raise EhelmError(st, self._lib.eh_last_error(self._ctx).decode())
+        return y
+
+    def power_Z(self, v0, iters, tol=1e-10, maxit=1000):
+        """Power-method estimates ||Z v_k|| of rho(Z(alpha)) (eh_power_Z);
+        v0 (one cell vector) is copied, not modified."""
+        _check_dev(v0, torch.complex128, self.ncell, "v0")
+        v = v0.clone()
+        est = (ctypes.c_double * int(iters))()
+        st = self._check(self._lib.eh_power_Z(self._ctx, _ptr(v), int(iters), float(tol), int(maxit), est))
+        if st == N.EH_NOT_CONVERGED:
+            raise EhelmError(st, self._lib.eh_last_error(self._ctx).decode())
+        return np.array(est[:]), v
+
     def misfit(self, u, rec, d):
         nrhs = self._nrhs(u, self.ndof)
         _check_dev(u, torch.complex128, nrhs * self.ndof, "u")

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "ehelm.h")).read()
-    return sorted(set(re.findall(r"\b(eh_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(eh_[A-Za-z_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -470,3 +470,33 @@ def test_tilde_Ap_variant_parity(n, levels):
     for k in range(2):
         assert rel(z[k], M.apply(r[k])) <= 1e-10
     g.close(); u.close()
+
+
+def test_block_solve_apply_Z_and_power_method():
+    """Block solves of the shifted blocks against sparse LU (FP64 multigrid,
+    1e-9), Z(alpha) v = Xi A_alpha^-1 B^T H_p,alpha^-1 v against the oracle's
+    matrix-free Z (1e-8), and the power method's estimates of rho(Z) against
+    the oracle's power method from the same start vector (1e-6)."""
+    say("block solve, Z mat-vec, power method")
+    import scipy.sparse.linalg as spla
+    from oracle.analysis import ZOperator, power_method
+    n, alpha = (32, 24), 0.3
+    g, s = make(n, seed=23, levels=3, alpha=alpha, mg_precision=64, restart=20)
+    for b in range(3):
+        X = s.H_p(alpha) if b == 2 else s.A_block(b, alpha)
+        f = crand((2, X.shape[0]), 90 + b)
+        x, info = g.block_solve(b, to_dev(f), tol=1e-11, maxit=500)
+        lu = spla.splu(X.tocsc())
+        xs = x.cpu().numpy()
+        for k in range(2):
+            assert info[k]["converged"]
+            assert rel(xs[k], lu.solve(f[k])) <= 1e-9, (b, k)
+    v = crand(s.ncell, 95)
+    Zop = ZOperator(s, alpha)
+    y = g.apply_Z(to_dev(v), tol=1e-12, maxit=500).cpu().numpy()
+    assert rel(y, Zop(v)) <= 1e-8
+    est, _ = g.power_Z(to_dev(v), 15, tol=1e-12, maxit=500)
+    ref = power_method(Zop, v, 15)
+    say(f"  rho(Z) estimates gpu {est[-1]:.6f} oracle {ref[-1]:.6f}")
+    np.testing.assert_allclose(est, ref, rtol=1e-6)
+    g.close()
