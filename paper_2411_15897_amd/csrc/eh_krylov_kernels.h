@@ -150,13 +150,6 @@ k_reduce_partials(int nblk, int m, int nrhs, const c128* __restrict__ partial, c
     if (threadIdx.x == 0) out[r * m + i] = mk(sre[0], sim[0]);
 }
 
-// out = s * in
-__global__ void __launch_bounds__(256)
-k_scal(int64_t n, double s, const c128* __restrict__ in, c128* __restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) out[p] = s * in[p];
-}
-
 // out = value (graph-safe fill)
 template <class V>
 __global__ void __launch_bounds__(256)

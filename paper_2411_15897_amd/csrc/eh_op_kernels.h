@@ -156,6 +156,13 @@ k_cast_scaled(int64_t n, const c128* __restrict__ in, int64_t vi, const double* 
         out[q * vo + i] = ccast<To>(sq * in[q * vi + i]);
 }
 
+// out = s * in (the power method's normalisation)
+__global__ void __launch_bounds__(256)
+k_scal(int64_t n, double s, const c128* __restrict__ in, c128* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) out[p] = s * in[p];
+}
+
 template <class To, class Ti>
 __global__ void __launch_bounds__(256)
 k_cast(int64_t n, const cplx<Ti>* __restrict__ in, cplx<To>* __restrict__ out) {

@@ -709,8 +709,8 @@ template <class T>
 void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, const int64_t* vf,
             void* const* out, const int64_t* vo, bool guess, int nrhs);
 
-inline bool fused_cycle(const eh_ctx* c, bool guess, int nrhs) {
-    (void)nrhs;
+// The fused legs cover 2D V(1, nu2) cycles started from a zero guess.
+inline bool fused_cycle(const eh_ctx* c, bool guess) {
     return c->o.fused && c->dim == 2 && c->o.cycle == 0 && c->o.nu_pre == 1 &&
            (c->o.nu_post == 1 || c->o.nu_post == 2) && !guess;
 }
@@ -861,7 +861,7 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
         return;
     }
     const int nu1 = c->o.nu_pre, nu2 = c->o.nu_post;
-    if (fused_cycle(c, guess, nrhs)) {
+    if (fused_cycle(c, guess)) {
         fused_level<T>(c, kinds, ns, l, f, vf, out, vo, nrhs);
         return;
     }
@@ -1135,7 +1135,7 @@ void maybe_autotune(eh_ctx* c, int nrhs) {
         int ns = 0;
         if (g == 0) kinds[ns++] = c->dim;
         else for (int k = 0; k < c->dim; ++k) kinds[ns++] = k;
-        if (fused_cycle(c, false, nrhs)) {
+        if (fused_cycle(c, false)) {
             // the fused legs are the only level kernels at this batch size
             for (int l = 0; l < L; ++l)
                 for (int s = 0; s < ns; ++s) {

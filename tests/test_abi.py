@@ -57,7 +57,7 @@ def _create(n, vp, vs, rho, omega=1.0, levels=2, dim=None, **kw):
 
 
 @pytest.mark.parametrize("case", ["vs>=vp", "rho<=0", "nan", "divisibility", "dim", "omega",
-                                  "precision", "restart", "levels"])
+                                  "precision", "restart", "levels", "fused", "ap_variant"])
 def test_invalid_arguments_are_rejected_before_device_work(case):
     n = (8, 8)
     vp, vs, rho = np.full(64, 2.0), np.full(64, 1.0), np.full(64, 1.0)
@@ -81,6 +81,10 @@ def test_invalid_arguments_are_rejected_before_device_work(case):
         kw["restart"] = 0
     elif case == "levels":
         levels = 0
+    elif case == "fused":
+        kw["fused"] = 2
+    elif case == "ap_variant":
+        kw["ap_variant"] = 3
     st, ctx, msg = _create(n, vp, vs, rho, omega=omega, levels=levels, dim=dim, **kw)
     assert st == N.EH_ERR_ARG
     assert ctx.value is None
@@ -91,5 +95,9 @@ def test_null_context_calls_are_argument_errors():
     L = N.lib()
     assert L.eh_apply_operator(None, None, None, 1) == N.EH_ERR_ARG
     assert L.eh_solve(None, None, None, 1, 1e-6, 10, None) == N.EH_ERR_ARG
+    assert L.eh_block_solve(None, 0, None, None, 1, 1e-6, 10, None) == N.EH_ERR_ARG
+    assert L.eh_apply_Z(None, None, None, 1e-6, 10) == N.EH_ERR_ARG
+    est = (ctypes.c_double * 2)()
+    assert L.eh_power_Z(None, None, 2, 1e-6, 10, est) == N.EH_ERR_ARG
     L.eh_destroy(None)
     assert L.eh_ndof(None) == 0
