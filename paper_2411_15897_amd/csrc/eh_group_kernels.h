@@ -15,6 +15,8 @@
 //   3  out = X u                               (operator)
 //   4  out = w D^-1 f and out2 = f - X out     (first sweep fused with the
 //      residual: the neighbours' w D^-1 f is recomputed from f and D)
+//   5  out = u1 + w D^-1 (f - X u1), u1 = w D^-1 f (the first two sweeps
+//      from a zero guess in one pass, u1 of the neighbours recomputed)
 #pragma once
 
 #include "eh_common.h"
@@ -96,16 +98,14 @@ k_gfine(GArgs<T> a, int nrhs) {
             off[2 * ax + 1] = hp ? (int)st[ax] : 0;
             cw[2 * ax] = mk<T>(hm ? c.cm[ax] : T(0), T(0));
             cw[2 * ax + 1] = mk<T>(hp ? c.cp[ax] : T(0), T(0));
-            if (MODE == 4) {
+            if (MODE == 4 || MODE == 5) {
                 // fold the neighbour's first-sweep factor damp / D_nb in
                 cw[2 * ax] = cw[2 * ax] * (hm ? cdiv(mk<T>(damp, T(0)), D[p + off[2 * ax]]) : czero<T>());
                 cw[2 * ax + 1] = cw[2 * ax + 1] * (hp ? cdiv(mk<T>(damp, T(0)), D[p + off[2 * ax + 1]]) : czero<T>());
             }
         }
     }
-    if (MODE == 4) {
-        cplx<T>* __restrict__ out2 = a.out2[slot];
-        const int64_t vo2 = a.vo2[slot];
+    if (MODE == 4 || MODE == 5) {
 #pragma unroll 2
         for (int r = 0; r < nrhs; ++r) {
             const cplx<T>* __restrict__ fr = f + r * vf;
@@ -114,8 +114,13 @@ k_gfine(GArgs<T> a, int nrhs) {
             cplx<T> s = czero<T>();
 #pragma unroll
             for (int t = 0; t < NN; ++t) s = s + cw[t] * fr[p + off[t]];
-            out[r * vo + p] = u0;
-            out2[r * vo2 + p] = fp - Dp * u0 + s;
+            const cplx<T> r0 = fp - Dp * u0 + s;
+            if (MODE == 4) {
+                out[r * vo + p] = u0;
+                a.out2[slot][r * a.vo2[slot] + p] = r0;
+            } else {
+                out[r * vo + p] = u0 + sc * r0;
+            }
         }
         return;
     }
@@ -186,14 +191,14 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
                                     (i + ox >= 0) && (i + ox < d.g[0]);
                     okmask |= ok ? (1u << o) : 0u;
                     cf[o] = ok ? coef[o * np + p] : czero<T>();
-                    if (MODE == 4) {
+                    if (MODE == 4 || MODE == 5) {
                         // neighbour's first-sweep factor damp / D_nb folded into the coefficient
                         cf[o] = cf[o] * (ok ? dinv[p + oz * sz + oy * sy + ox] : czero<T>());
                     }
                 }
 #pragma unroll 1
         for (int r = 0; r < nrhs; ++r) {
-            const cplx<T>* __restrict__ src = (MODE == 4) ? f + r * vf : u + r * vu;
+            const cplx<T>* __restrict__ src = (MODE == 4 || MODE == 5) ? f + r * vf : u + r * vu;
             cplx<T> xu = czero<T>();
 #pragma unroll
             for (int oz = -WZ; oz <= WZ; ++oz)
@@ -209,9 +214,11 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
             if (MODE == 1) out[r * vo + p] = src[p] + sc * (fp - xu);
             else if (MODE == 2) out[r * vo + p] = fp - xu;
             else if (MODE == 3) out[r * vo + p] = xu;
-            else {
+            else if (MODE == 4) {
                 out[r * vo + p] = sc * fp;
                 a.out2[slot][r * a.vo2[slot] + p] = fp - xu;
+            } else {
+                out[r * vo + p] = sc * fp + sc * (fp - xu);
             }
         }
         return;
@@ -232,7 +239,7 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
                     const int o = ((oz + WZ) * NY + (oy + WY)) * NX + (ox + WX);
                     const int64_t q = p + oz * sz + oy * sy + ox;
                     cplx<T> v;
-                    if (MODE == 4) v = dinv[q] * fr[q];
+                    if (MODE == 4 || MODE == 5) v = dinv[q] * fr[q];
                     else v = ur[q];
                     xu = xu + coef[o * np + p] * v;
                 }
@@ -244,9 +251,11 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
             out[r * vo + p] = fr[p] - xu;
         } else if (MODE == 3) {
             out[r * vo + p] = xu;
-        } else {
+        } else if (MODE == 4) {
             out[r * vo + p] = sc * fr[p];
             a.out2[slot][r * a.vo2[slot] + p] = fr[p] - xu;
+        } else {
+            out[r * vo + p] = sc * fr[p] + sc * (fr[p] - xu);
         }
     }
 }

@@ -650,12 +650,13 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
         const Block& B = c->blk[a.kind[s]];
         const double np = (double)a.d[s].np(), cs = sizeof(cplx<T>), rs = sizeof(T);
         double coefb = l == 0 ? np * (cs + fine_couplings(c, P) * rs) : np * B.lev[l].w.nst() * cs;
-        double vecb = (mode == 0 || mode == 3) ? 2 * np * cs : (mode == 4 ? 3 * np * cs : 3 * np * cs);
+        double vecb = (mode == 0 || mode == 3 || mode == 5) ? 2 * np * cs : 3 * np * cs;
         if (mode == 0) coefb = np * cs;
         by += coefb + nrhs * vecb;
     }
     const int cls = l > 0 ? KC_COARSE
-                          : (mode == 0 || mode == 4 ? KC_FINE_FIRST : (mode == 1 ? KC_FINE_SWEEP : KC_FINE_RESID));
+                          : (mode == 0 || mode == 4 || mode == 5 ? KC_FINE_FIRST
+                                                                  : (mode == 1 ? KC_FINE_SWEEP : KC_FINE_RESID));
     Timed tm(c, cls, by);
     const dim3 blk = shape_block(c, group_of(c, kind0), l, 0);
     const dim3 g = ggrid(a, blk);
@@ -667,7 +668,8 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
         case 1: EH_GF(KIND, DIM, 1); break;     \
         case 2: EH_GF(KIND, DIM, 2); break;     \
         case 3: EH_GF(KIND, DIM, 3); break;     \
-        default: EH_GF(KIND, DIM, 4); break;    \
+        case 4: EH_GF(KIND, DIM, 4); break;     \
+        default: EH_GF(KIND, DIM, 5); break;    \
     }
         if (c->dim == 2) {
             if (P && a.tilde) { EH_GF_M(2, 2) } else if (P) { EH_GF_M(1, 2) } else { EH_GF_M(0, 2) }
@@ -686,7 +688,8 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
         case 1: EH_GS(DIM, 1); break;       \
         case 2: EH_GS(DIM, 2); break;       \
         case 3: EH_GS(DIM, 3); break;       \
-        default: EH_GS(DIM, 4); break;      \
+        case 4: EH_GS(DIM, 4); break;       \
+        default: EH_GS(DIM, 5); break;      \
     }
         if (c->dim == 2) { EH_GS_M(2) } else { EH_GS_M(3) }
 #undef EH_GS_M
@@ -915,16 +918,17 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
         nb = 1;
         have_resid = true;
     } else if (nu1 > 1) {
+        // the first two sweeps from zero in one pass
         for (int s = 0; s < ns; ++s) {
             a.f[s] = (const cplx<T>*)f[s];
             a.vf[s] = vf[s];
             a.out[s] = (cplx<T>*)L[s]->u;
             a.vo[s] = np[s];
         }
-        gsweep<T>(c, a, l, 0, nrhs);
+        gsweep<T>(c, a, l, 5, nrhs);
         for (int s = 0; s < ns; ++s) { cur[s] = L[s]->u; vcur[s] = np[s]; }
         nb = 1;
-        for (int t = 1; t < nu1; ++t) sweep(1, false);
+        for (int t = 2; t < nu1; ++t) sweep(1, false);
     } else {
         for (int s = 0; s < ns; ++s) {
             hipLaunchKernelGGL((k_fill<cplx<T>>), dim3(lin_grid(np[s] * nrhs, 256, 4096)), dim3(256), 0, c->s,
