@@ -220,7 +220,7 @@ def config(k: int, scale: int = 1) -> Workload:
         src = [(1, ((32 + 64 * s) // scale, 1)) for s in range(32)]
         return Workload("config4_layered_2048_b32", n, h, vp, vs, rho, omega,
                         abc_width=20, abc_sides=abc_all_but_top(2),
-                        sources=src, levels=7, alpha=0.7, restart=10)
+                        sources=src, levels=7, alpha=0.7, restart=6)
     if k == 5:
         n = (192 // scale,) * 3
         vp, vs, rho = layered_inclusion_medium_3d(n, seed=4)
@@ -232,7 +232,7 @@ def config(k: int, scale: int = 1) -> Workload:
         return Workload("config5_layered_192cube", n, h, vp, vs, rho, omega,
                         abc_width=max(12 // scale, 1), abc_sides=abc_all_but_top(3),
                         sources=src, levels=5, nu=(2, 2),
-                        damping=(0.8, 0.8, 0.2), alpha=0.8, restart=10,
+                        damping=(0.8, 0.8, 0.2), alpha=0.8, restart=6,
                         intergrid="mixed")
     raise ValueError(f"unknown config {k}")
 
