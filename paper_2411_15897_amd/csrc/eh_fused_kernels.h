@@ -47,7 +47,7 @@ namespace eh {
 struct FCfg {
     int x, y, threads;
 };
-constexpr FCfg kFDown[] = {{32, 8, 256}, {32, 8, 512}, {16, 8, 256}, {8, 4, 128}};
+constexpr FCfg kFDown[] = {{32, 8, 256}, {32, 8, 512}, {16, 8, 256}, {7, 3, 128}};
 constexpr FCfg kFUp[] = {{64, 16, 1024}, {64, 8, 512}, {32, 8, 256}, {16, 8, 128}};
 constexpr int kFCfgs = 4;
 constexpr int FUSE_MAXW = 2;
@@ -150,8 +150,19 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
     cplx<T>* RR = lds + UX * UY;
     using RXW = R1<(NM & 1) != 0, MIXED>;
     using RYW = R1<(NM & 2) != 0, MIXED>;
+    // Small tiles with at most one support point per thread load that
+    // point's operator once, before the first barrier, and keep it for
+    // every right-hand side.
+    constexpr bool ONE_R = RX * RY <= NT;
+    const int my_ry = (int)threadIdx.x / RX, my_rx = (int)threadIdx.x - my_ry * RX;
+    const int mgx = rx0 + my_rx, mgy = ry0 + my_ry;
+    const bool rin = ONE_R && (int)threadIdx.x < RX * RY && mgx >= 0 && mgx < nx && mgy >= 0 && mgy < ny;
+    const int64_t rp = (int64_t)mgy * nx + mgx;
+    PointOp<T, FINE, KIND, WX, WY> rop;
+    if (rin) rop.load(a, slot, d, mgx, mgy, rp);
     for (int r = 0; r < nrhs; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
+        const cplx<T> fr = rin ? f[rp] : czero<T>();
         if (r > 0) __syncthreads();                 // LDS of the previous RHS consumed
 #pragma unroll 1
         for (int it = 0; it < (UX * UY + NT - 1) / NT; ++it) {
@@ -167,21 +178,26 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
             U[q] = v;
         }
         __syncthreads();
+        if (ONE_R) {
+            if ((int)threadIdx.x < RX * RY)
+                RR[threadIdx.x] = rin ? fr - rop.template apply<UX>(U, (my_ry + WY) * UX + (my_rx + WX)) : czero<T>();
+        } else {
 #pragma unroll 1
-        for (int it = 0; it < (RX * RY + NT - 1) / NT; ++it) {
-            const int q = threadIdx.x + it * NT;
-            if (q >= RX * RY) break;
-            const int ry = q / RX, rx = q - ry * RX;
-            const int gx = rx0 + rx, gy = ry0 + ry;
-            cplx<T> v = czero<T>();
-            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-                const int64_t p = (int64_t)gy * nx + gx;
-                const int l = (ry + WY) * UX + (rx + WX);
-                PointOp<T, FINE, KIND, WX, WY> op;
-                op.load(a, slot, d, gx, gy, p);
-                v = f[p] - op.template apply<UX>(U, l);
+            for (int it = 0; it < (RX * RY + NT - 1) / NT; ++it) {
+                const int q = threadIdx.x + it * NT;
+                if (q >= RX * RY) break;
+                const int ry = q / RX, rx = q - ry * RX;
+                const int gx = rx0 + rx, gy = ry0 + ry;
+                cplx<T> v = czero<T>();
+                if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                    const int64_t p = (int64_t)gy * nx + gx;
+                    const int l = (ry + WY) * UX + (rx + WX);
+                    PointOp<T, FINE, KIND, WX, WY> op;
+                    op.load(a, slot, d, gx, gy, p);
+                    v = f[p] - op.template apply<UX>(U, l);
+                }
+                RR[q] = v;
             }
-            RR[q] = v;
         }
         __syncthreads();
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
@@ -257,10 +273,12 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     constexpr int BX = TX + 2 * WX, BY = TY + 2 * WY;     // first of two sweeps
     constexpr int RING = BX * BY - TX * TY;               // its points outside the tile
     static_assert(RING <= NT, "at most one ring point per thread");
-    // small operators (fine level, 3x3 stencils) of the ring point are
-    // loaded up front with the own point's, so that every global load of
-    // the kernel is issued before the first barrier
-    constexpr bool RING_EARLY = FINE || (2 * WX + 1) * (2 * WY + 1) <= 9;
+    // small operators (fine level, 3x3 stencils) of the ring point, and any
+    // operator in the small-tile configuration (meant for the small levels,
+    // where registers do not limit the few resident workgroups), are loaded
+    // up front with the own point's, so that every global load of the kernel
+    // is issued before the first barrier
+    constexpr bool RING_EARLY = FINE || (2 * WX + 1) * (2 * WY + 1) <= 9 || NT <= 128;
     cplx<T>* A = lds;
     cplx<T>* B = lds + AX * AY;
     const int64_t csy = dc.g[0];
