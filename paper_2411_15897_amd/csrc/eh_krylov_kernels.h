@@ -21,7 +21,7 @@ constexpr int KRY_MAXM = 32;   // columns handled by one pass
 //         (projections of w and the newest column of the Gram matrix V^H V)
 // grid: (nblk, nrhs); block b owns the KRY_E * 256 entries starting at
 // b * KRY_E * 256 (each thread KRY_E of them, 256 apart: coalesced).
-// partial layout [r][blk][i] (i < m, or 1 for norms); coef layout [r][i].
+// partial layout [r][i][blk] (i < m, or 1 for norms); coef layout [r][i].
 constexpr int KRY_E = 4;
 template <int MODE>
 __global__ void __launch_bounds__(KRY_THREADS)
@@ -123,19 +123,30 @@ k_gs(int64_t n, int m, int nrhs, const c128* __restrict__ V, const c128* w,
         const int t = threadIdx.x;
         const double sr = (lre[0][t] + lre[1][t]) + (lre[2][t] + lre[3][t]);
         const double si = (lim[0][t] + lim[1][t]) + (lim[2][t] + lim[3][t]);
-        partial[((int64_t)r * nblk + blockIdx.x) * mm + t] = mk(sr, si);
+        partial[((int64_t)r * mm + t) * nblk + blockIdx.x] = mk(sr, si);
     }
 }
 
-// out[r][i] = sum_blk partial[r][blk][i]: one block per (i, r), fixed-order
+// out[r][i] = sum_blk partial[r][i][blk]: one block per (i, r), fixed-order
 // tree, so the result does not depend on timing.
 __global__ void __launch_bounds__(256)
 k_reduce_partials(int nblk, int m, int nrhs, const c128* __restrict__ partial, c128* __restrict__ out) {
     __shared__ double sre[256], sim[256];
     const int i = blockIdx.x, r = blockIdx.y;
+    const c128* pr = partial + ((int64_t)r * m + i) * nblk;
     double ar = 0.0, ai = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) {
-        const c128 v = partial[((int64_t)r * nblk + b) * m + i];
+    // eight partials in flight per thread, then the remainder (fixed order)
+    constexpr int U = 8;
+    int b = threadIdx.x;
+    for (; b + (U - 1) * 256 < nblk; b += U * 256) {
+        c128 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = pr[b + u * 256];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { ar += v[u].re; ai += v[u].im; }
+    }
+    for (; b < nblk; b += 256) {
+        const c128 v = pr[b];
         ar += v.re; ai += v.im;
     }
     sre[threadIdx.x] = ar; sim[threadIdx.x] = ai;

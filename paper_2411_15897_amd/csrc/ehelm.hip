@@ -137,7 +137,6 @@ struct eh_ctx {
     double* d_rho = nullptr;
     double* d_gamma = nullptr;
     double* d_lm = nullptr;       // lambda + mu
-    double* d_edgecnt = nullptr;  // unused placeholder
     Block blk[4];
     int nblocks = 3;
     int nrhs_cap = 0;
