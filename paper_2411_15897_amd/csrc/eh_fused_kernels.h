@@ -93,7 +93,7 @@ __device__ __forceinline__ cplx<T> fuse_sc(const GArgs<T>& a, int slot, int64_t 
 // not depend on which tile, or which phase of a tile, computes it.  The up
 // leg keeps its own tile point's operator for both sweeps and every
 // right-hand side.
-template <class T, bool FINE, int KIND, int WX, int WY>
+template <class T, bool FINE, int KIND, int WX, int WY, bool HALF = false>
 struct PointOp {
     static constexpr int NST = (2 * WX + 1) * (2 * WY + 1);
     cplx<T> cf[FINE ? 1 : NST];
@@ -107,7 +107,13 @@ struct PointOp {
         } else {
             const int64_t np = d.np();
 #pragma unroll
-            for (int o = 0; o < (FINE ? 1 : NST); ++o) cf[o] = a.coef[slot][o * np + p];
+            for (int o = 0; o < (FINE ? 1 : NST); ++o) {
+                const int oy = o / (2 * WX + 1) - WY, ox = o % (2 * WX + 1) - WX;
+                const bool ok = !HALF || o >= NST / 2 ||
+                                (gx + ox >= 0 && gx + ox < d.g[0] && gy + oy >= 0 && gy + oy < d.g[1]);
+                cf[o] = ok ? stencil_coef<T, FINE ? 1 : NST, HALF>(a.coef[slot], np, o, p, p + oy * d.g[0] + ox)
+                           : czero<T>();
+            }
         }
     }
     // X u with u from an LDS array of row pitch SX at local index l
@@ -158,7 +164,7 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
     const int mgx = rx0 + my_rx, mgy = ry0 + my_ry;
     const bool rin = ONE_R && (int)threadIdx.x < RX * RY && mgx >= 0 && mgx < nx && mgy >= 0 && mgy < ny;
     const int64_t rp = (int64_t)mgy * nx + mgx;
-    PointOp<T, FINE, KIND, WX, WY> rop;
+    PointOp<T, FINE, KIND, WX, WY, !FINE && NM != 0 && !MIXED> rop;
     if (rin) rop.load(a, slot, d, mgx, mgy, rp);
     for (int r = 0; r < nrhs; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
@@ -192,7 +198,7 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
                 if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
                     const int64_t p = (int64_t)gy * nx + gx;
                     const int l = (ry + WY) * UX + (rx + WX);
-                    PointOp<T, FINE, KIND, WX, WY> op;
+                    PointOp<T, FINE, KIND, WX, WY, !FINE && NM != 0 && !MIXED> op;
                     op.load(a, slot, d, gx, gy, p);
                     v = f[p] - op.template apply<UX>(U, l);
                 }
@@ -260,7 +266,7 @@ k_fdown(GArgs<T> a, int nrhs) {
 // up leg: a.d = level l, a.dc = level l+1, a.f = f_l (vf), a.u = e_{l+1}
 // (vu), a.out = e_l (vo)
 
-template <class T, bool FINE, int KIND, int WX, int WY, int NM, int NU2, int TX, int TY, int NT>
+template <class T, bool FINE, int KIND, int WX, int WY, int NM, int NU2, int TX, int TY, int NT, bool HALF>
 __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* lds, int nrhs, int tile_x,
                                         int tile_y) {
     static_assert(TX * TY == NT, "one tile point per thread");
@@ -287,7 +293,7 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     const int mgx = tx0 + my_x, mgy = ty0 + my_y;
     const bool mine = mgx < nx && mgy < ny;
     const int64_t mp = (int64_t)mgy * nx + mgx;
-    PointOp<T, FINE, KIND, WX, WY> op;
+    PointOp<T, FINE, KIND, WX, WY, HALF> op;
     if (mine) op.load(a, slot, d, mgx, mgy, mp);
     // this thread's ring point (first sweep only)
     int rbx = 0, rby = 0;
@@ -307,7 +313,7 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     const int rgx = tx0 - WX + rbx, rgy = ty0 - WY + rby;
     const bool ring = NU2 == 2 && (int)threadIdx.x < RING && rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny;
     const int64_t rp = (int64_t)rgy * nx + rgx;
-    PointOp<T, FINE, KIND, WX, WY> rop;
+    PointOp<T, FINE, KIND, WX, WY, HALF> rop;
     if (RING_EARLY && ring) rop.load(a, slot, d, rgx, rgy, rp);
     for (int r = 0; r < nrhs; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
@@ -362,7 +368,7 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
                     v = rop.template sweep<AX>(A, l, fring);
                 } else if (ring) {
                     // wide stencils: loaded here, not held across the batch
-                    PointOp<T, FINE, KIND, WX, WY> wop;
+                    PointOp<T, FINE, KIND, WX, WY, HALF> wop;
                     wop.load(a, slot, d, rgx, rgy, rp);
                     v = wop.template sweep<AX>(A, l, fring);
                 }
@@ -390,20 +396,22 @@ k_fup(GArgs<T> a, int nrhs) {
     const int kind = a.kind[slot];
     int tx, ty;
     xcd_tile(tx, ty);
-#define EH_FU(FI, KI, WX, WY, NM) up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT>(a, slot, lds, nrhs, tx, ty)
+#define EH_FU(FI, KI, WX, WY, NM, HF) \
+    up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT, HF>(a, slot, lds, nrhs, tx, ty)
     if (FINE) {
-        if (kind == 2 && a.tilde) EH_FU(true, 2, 1, 1, 0);
-        else if (kind == 2) EH_FU(true, 1, 1, 1, 0);
-        else if (kind == 0) EH_FU(true, 0, 1, 1, 1);
-        else EH_FU(true, 0, 1, 1, 2);
+        if (kind == 2 && a.tilde) EH_FU(true, 2, 1, 1, 0, false);
+        else if (kind == 2) EH_FU(true, 1, 1, 1, 0, false);
+        else if (kind == 0) EH_FU(true, 0, 1, 1, 1, false);
+        else EH_FU(true, 0, 1, 1, 2, false);
     } else if (a.mixed) {
-        if (kind == 2) EH_FU(false, 0, 1, 1, 0);
-        else if (kind == 0) EH_FU(false, 0, 1, 1, 1);
-        else EH_FU(false, 0, 1, 1, 2);
+        if (kind == 2) EH_FU(false, 0, 1, 1, 0, false);
+        else if (kind == 0) EH_FU(false, 0, 1, 1, 1, false);
+        else EH_FU(false, 0, 1, 1, 2, false);
     } else {
-        if (kind == 2) EH_FU(false, 0, 2, 2, 0);
-        else if (kind == 0) EH_FU(false, 0, 1, 2, 1);
-        else EH_FU(false, 0, 2, 1, 2);
+        // full weighting: the shear blocks' stencils are stored half
+        if (kind == 2) EH_FU(false, 0, 2, 2, 0, false);
+        else if (kind == 0) EH_FU(false, 0, 1, 2, 1, true);
+        else EH_FU(false, 0, 2, 1, 2, true);
     }
 #undef EH_FU
 }

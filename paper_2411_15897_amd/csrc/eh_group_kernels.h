@@ -146,6 +146,22 @@ k_gfine(GArgs<T> a, int nrhs) {
 // ---------------------------------------------------------------------------
 // coarse levels (stored Galerkin stencils)
 
+// Coefficient of stencil offset o at point p of a stored Galerkin stencil
+// (offsets enumerated x fastest over a centrally symmetric box, so offset
+// NST-1-o is the mirror of o).  The shear blocks A_k are complex symmetric
+// and full weighting R = P^T / 2^d keeps that on every level, so for them
+// (HALF) only the offsets o >= CENTRE are stored: offset o < CENTRE at p equals the
+// mirrored offset stored at the neighbour q = p + offset(o), which the
+// caller guarantees to lie in the grid.
+template <class T, int NST, bool HALF>
+__device__ __forceinline__ cplx<T> stencil_coef(const cplx<T>* __restrict__ coef, int64_t np, int o, int64_t p,
+                                                int64_t q) {
+    constexpr int C = NST / 2;
+    if (!HALF) return coef[o * np + p];
+    if (o >= C) return coef[(o - C) * np + p];
+    return coef[(NST - 1 - o - C) * np + q];
+}
+
 // dinv = damping / centre coefficient, once per level at setup
 template <class T, int CENTRE>
 __global__ void k_dinv(int64_t np, const cplx<T>* __restrict__ coef, T damp, cplx<T>* __restrict__ dinv) {
@@ -153,7 +169,7 @@ __global__ void k_dinv(int64_t np, const cplx<T>* __restrict__ coef, T damp, cpl
     if (p < np) dinv[p] = cdiv(mk<T>(damp, T(0)), coef[CENTRE * np + p]);
 }
 
-template <class T, int WX, int WY, int WZ, int MODE>
+template <class T, int WX, int WY, int WZ, int MODE, bool HALF>
 __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const Dims& d, int i, int j, int k,
                                              int64_t p, int64_t sy, int64_t sz, int nrhs) {
     const int64_t np = d.np();
@@ -190,7 +206,7 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
                     const bool ok = (k + oz >= 0) && (k + oz < d.g[2]) && (j + oy >= 0) && (j + oy < d.g[1]) &&
                                     (i + ox >= 0) && (i + ox < d.g[0]);
                     okmask |= ok ? (1u << o) : 0u;
-                    cf[o] = ok ? coef[o * np + p] : czero<T>();
+                    cf[o] = ok ? stencil_coef<T, NST, HALF>(coef, np, o, p, p + oz * sz + oy * sy + ox) : czero<T>();
                     if (MODE == 4 || MODE == 5) {
                         // neighbour's first-sweep factor damp / D_nb folded into the coefficient
                         cf[o] = cf[o] * (ok ? dinv[p + oz * sz + oy * sy + ox] : czero<T>());
@@ -241,7 +257,7 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
                     cplx<T> v;
                     if (MODE == 4 || MODE == 5) v = dinv[q] * fr[q];
                     else v = ur[q];
-                    xu = xu + coef[o * np + p] * v;
+                    xu = xu + stencil_coef<T, NST, HALF>(coef, np, o, p, q) * v;
                 }
             }
         }
@@ -267,19 +283,21 @@ __global__ void __launch_bounds__(256)
 k_gstencil(GArgs<T> a, int nrhs) {
     EH_GROUP_POINT(a, d)
     const int kind = a.kind[slot];
+    // with full weighting, kinds below DIM are the symmetric, half-stored
+    // shear blocks (the mixed restriction is not P^T / 2^d: stored in full)
     if (MIXED) {
-        stencil_body<T, 1, 1, (DIM == 3 ? 1 : 0), MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        stencil_body<T, 1, 1, (DIM == 3 ? 1 : 0), MODE, false>(a, slot, d, i, j, k, p, sy, sz, nrhs);
         return;
     }
     if (DIM == 2) {
-        if (kind == 0) stencil_body<T, 1, 2, 0, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else if (kind == 1) stencil_body<T, 2, 1, 0, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else stencil_body<T, 2, 2, 0, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        if (kind == 0) stencil_body<T, 1, 2, 0, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else if (kind == 1) stencil_body<T, 2, 1, 0, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else stencil_body<T, 2, 2, 0, MODE, false>(a, slot, d, i, j, k, p, sy, sz, nrhs);
     } else {
-        if (kind == 0) stencil_body<T, 1, 2, 2, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else if (kind == 1) stencil_body<T, 2, 1, 2, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else if (kind == 2) stencil_body<T, 2, 2, 1, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else stencil_body<T, 2, 2, 2, MODE>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        if (kind == 0) stencil_body<T, 1, 2, 2, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else if (kind == 1) stencil_body<T, 2, 1, 2, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else if (kind == 2) stencil_body<T, 2, 2, 1, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        else stencil_body<T, 2, 2, 2, MODE, false>(a, slot, d, i, j, k, p, sy, sz, nrhs);
     }
 }
 

@@ -56,7 +56,8 @@ struct StateError {
 struct Level {
     Dims d{};
     Widths w{};              // stencil half widths (levels >= 1)
-    void* coef = nullptr;    // levels >= 1: [nst][np] complex, multigrid precision
+    bool half = false;       // symmetric stencil: only offsets from the centre on are stored
+    void* coef = nullptr;    // levels >= 1: [stored offsets][np] complex, multigrid precision
     void* dinv = nullptr;    // levels >= 1: damping / diagonal, multigrid precision
     void* f = nullptr;       // right-hand side          (nrhs_cap * np)
     void* u = nullptr;       // iterate                  (nrhs_cap * np)
@@ -64,6 +65,7 @@ struct Level {
     void* r = nullptr;       // residual                 (nrhs_cap * np)
     void* e = nullptr;       // cycle result             (nrhs_cap * np)
     double damp = 0.8;
+    int nstored() const { return half ? (w.nst() + 1) / 2 : w.nst(); }
 };
 
 struct Block {
@@ -487,36 +489,43 @@ void build_hierarchy(eh_ctx* c, Block& B, const std::vector<c128>& st0) {
                            prev, Lc.d, wc, B.nodal_mask, c->o.intergrid, cur, overflow);
         HIPCHK(hipGetLastError());
         HIPCHK(hipDeviceSynchronize());
-        // store in the multigrid precision
+        // store in the multigrid precision; with full weighting the shear
+        // blocks stay complex symmetric, so only the offsets from the centre
+        // on are kept (the others are read from the neighbours); H_p and
+        // the mixed intergrid's operators in full
+        Lc.half = B.kind < c->dim && c->o.intergrid == 0;
+        const int ctr_full = wc.nst() / 2;
+        const int64_t nst_st = Lc.nstored();
+        const c128* src = Lc.half ? cur + (int64_t)ctr_full * npc : cur;
         if (f32) {
-            c64* cf = c->alloc<c64>((size_t)wc.nst() * npc);
-            hipLaunchKernelGGL((k_cast<float, double>), dim3(lin_grid((int64_t)wc.nst() * npc)), dim3(256), 0, 0,
-                               (int64_t)wc.nst() * npc, cur, cf);
+            c64* cf = c->alloc<c64>((size_t)nst_st * npc);
+            hipLaunchKernelGGL((k_cast<float, double>), dim3(lin_grid(nst_st * npc)), dim3(256), 0, 0, nst_st * npc,
+                               src, cf);
             HIPCHK(hipGetLastError());
             Lc.coef = cf;
         } else {
-            c128* cf = c->alloc<c128>((size_t)wc.nst() * npc);
-            HIPCHK(hipMemcpy(cf, cur, (size_t)wc.nst() * npc * sizeof(c128), hipMemcpyDeviceToDevice));
+            c128* cf = c->alloc<c128>((size_t)nst_st * npc);
+            HIPCHK(hipMemcpy(cf, src, (size_t)nst_st * npc * sizeof(c128), hipMemcpyDeviceToDevice));
             Lc.coef = cf;
         }
         {
             // damping / centre coefficient of the stored stencil
-            const int ctr = (wc.w[2] * (2 * wc.w[1] + 1) + wc.w[1]) * (2 * wc.w[0] + 1) + wc.w[0];
+            const int ctr = Lc.half ? 0 : ctr_full;
             const unsigned gl = (unsigned)((npc + 255) / 256);
             if (f32) {
                 Lc.dinv = c->alloc<c64>(npc);
 #define EH_DI(CT) hipLaunchKernelGGL((k_dinv<float, CT>), dim3(gl), dim3(256), 0, 0, npc, (const c64*)Lc.coef, \
                                      (float)Lc.damp, (c64*)Lc.dinv)
-                if (ctr == 7) EH_DI(7); else if (ctr == 12) EH_DI(12); else if (ctr == 37) EH_DI(37);
-                else if (ctr == 62) EH_DI(62); else if (ctr == 4) EH_DI(4); else if (ctr == 13) EH_DI(13);
+                if (ctr == 0) EH_DI(0); else if (ctr == 12) EH_DI(12); else if (ctr == 62) EH_DI(62);
+                else if (ctr == 4) EH_DI(4); else if (ctr == 13) EH_DI(13);
                 else throw ArgError{"internal: unexpected stencil centre"};
 #undef EH_DI
             } else {
                 Lc.dinv = c->alloc<c128>(npc);
 #define EH_DI(CT) hipLaunchKernelGGL((k_dinv<double, CT>), dim3(gl), dim3(256), 0, 0, npc, (const c128*)Lc.coef, \
                                      Lc.damp, (c128*)Lc.dinv)
-                if (ctr == 7) EH_DI(7); else if (ctr == 12) EH_DI(12); else if (ctr == 37) EH_DI(37);
-                else if (ctr == 62) EH_DI(62); else if (ctr == 4) EH_DI(4); else if (ctr == 13) EH_DI(13);
+                if (ctr == 0) EH_DI(0); else if (ctr == 12) EH_DI(12); else if (ctr == 62) EH_DI(62);
+                else if (ctr == 4) EH_DI(4); else if (ctr == 13) EH_DI(13);
                 else throw ArgError{"internal: unexpected stencil centre"};
 #undef EH_DI
             }
@@ -648,7 +657,7 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
     for (int s = 0; s < a.ns; ++s) {
         const Block& B = c->blk[a.kind[s]];
         const double np = (double)a.d[s].np(), cs = sizeof(cplx<T>), rs = sizeof(T);
-        double coefb = l == 0 ? np * (cs + fine_couplings(c, P) * rs) : np * B.lev[l].w.nst() * cs;
+        double coefb = l == 0 ? np * (cs + fine_couplings(c, P) * rs) : np * B.lev[l].nstored() * cs;
         double vecb = (mode == 0 || mode == 3 || mode == 5) ? 2 * np * cs : 3 * np * cs;
         if (mode == 0) coefb = np * cs;
         by += coefb + nrhs * vecb;
@@ -790,7 +799,7 @@ void fused_level(eh_ctx* c, const int* kinds, int ns, int l, const void* const* 
         const Level& Lv = B.lev[l];
         const Level& Cv = B.lev[l + 1];
         const double np = (double)Lv.d.np(), npc = (double)Cv.d.np();
-        cbytes += l == 0 ? np * (cs + fine_couplings(c, P) * rs) : np * (Lv.w.nst() + 1) * cs;
+        cbytes += l == 0 ? np * (cs + fine_couplings(c, P) * rs) : np * (Lv.nstored() + 1) * cs;
         vdown += (np + npc) * cs;
         vup += (2 * np + npc) * cs;
         cf[s] = Cv.f; ce[s] = Cv.e; vcv[s] = Cv.d.np();
