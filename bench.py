@@ -97,7 +97,8 @@ def sources_sha256(files):
 def pmc_summary(fetch_csv, write_csv, kernel, workload):
     """HBM traffic per timed launch of a kernel class from a FETCH_SIZE and a
     WRITE_SIZE rocprofv3 counter run (KiB per dispatch), each scaled by what
-    the same counter reads for the 1 GiB calibration copy of the same run."""
+    the same counter reads for the 1 GiB calibration copy of the same run
+    (the run's first copy dispatch: it precedes the solver's own copies)."""
     import csv
     members, leads = CLASS_KERNELS[kernel]
     leads = leads or members
@@ -105,8 +106,9 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
     total = 0.0
     for tag, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
-        copies = [float(r["Counter_Value"]) for r in rows if "__amd_rocclr_copyBuffer" in r["Kernel_Name"]]
-        ref = max(copies)                               # the 1 GiB copy
+        copies = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows
+                        if "__amd_rocclr_copyBuffer" in r["Kernel_Name"])
+        ref = copies[0][1]                              # the 1 GiB calibration copy
         scale = (1 << 30) / 1024.0 / ref
         cls = [r for r in rows if any(m in r["Kernel_Name"] for m in members)]
         nlaunch = sum(1 for r in cls if any(m in r["Kernel_Name"] for m in leads))
@@ -132,17 +134,18 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
     return rec
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs, or None when none was recorded for that
-    kernel class or the kernel sources changed since (sha256 mismatch)."""
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None when none was recorded
+    for that kernel class and workload or the kernel sources changed since
+    (sha256 mismatch)."""
     import glob
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.txt")):
         try:
             rec = json.load(open(path))
         except (OSError, ValueError):
             continue
-        if rec.get("kernel_class") != kernel:
+        if rec.get("kernel_class") != kernel or rec.get("workload") != workload:
             continue
         if sources_sha256(rec["source_files"]) != rec["source_sha256"]:
             return None
@@ -202,7 +205,7 @@ def main():
         return ElasticHelmholtz(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, levels=wl.levels,
                                 nu=wl.nu, damping=wl.damping, alpha=wl.alpha, mg_precision=prec,
                                 restart=wl.restart, abc_width=wl.abc_width,
-                                abc_sides=wl.abc_sides)
+                                abc_sides=wl.abc_sides, intergrid=wl.intergrid)
 
     def timed(solver, steps, warmup, kernel=None):
         for w in range(warmup):
@@ -283,7 +286,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-        "traffic": recorded_traffic(kernel),
+        "traffic": recorded_traffic(kernel, wl.name),
         "launches": launches,
         "avg_us": avg_ms * 1e3,
         "algorithmic_bytes_per_launch": nbytes / max(launches, 1),

@@ -1,5 +1,6 @@
 """bench.py's counter summariser on a small synthetic counter file (no GPU):
-the 1 GiB calibration copy fixes the scale of each counter, dispatches of a
+the 1 GiB calibration copy (the run's first copy, not a later larger one)
+fixes the scale of each counter, dispatches of a
 class are summed and divided by its timed launches (a Gram-Schmidt pass is
 two dispatches), and the record carries the hash of the kernel sources."""
 import csv
@@ -23,11 +24,13 @@ def test_pmc_summary_scales_by_the_copy_and_counts_timed_launches(tmp_path):
     fetch = [("__amd_rocclr_copyBuffer", gib_kib / 2),          # the counter reads half
              ("void eh::k_gs<4>(long, int)", 1000.0), ("eh::k_reduce_partials(int)", 10.0),
              ("void eh::k_gs<2>(long, int)", 2000.0), ("eh::k_reduce_partials(int)", 10.0),
-             ("void eh::k_fup<float, true, 2, 0>(eh::GArgs<float>, int)", 5000.0)]
+             ("void eh::k_fup<float, true, 2, 0>(eh::GArgs<float>, int)", 5000.0),
+             ("__amd_rocclr_copyBuffer", gib_kib)]                # a later, larger copy of the solver
     write = [("__amd_rocclr_copyBuffer", gib_kib),
              ("void eh::k_gs<4>(long, int)", 0.0), ("eh::k_reduce_partials(int)", 1.0),
              ("void eh::k_gs<2>(long, int)", 500.0), ("eh::k_reduce_partials(int)", 1.0),
-             ("void eh::k_fup<float, true, 2, 0>(eh::GArgs<float>, int)", 900.0)]
+             ("void eh::k_fup<float, true, 2, 0>(eh::GArgs<float>, int)", 900.0),
+             ("__amd_rocclr_copyBuffer", 2 * gib_kib)]
     f, w = tmp_path / "fetch.csv", tmp_path / "write.csv"
     _write(f, "FETCH_SIZE", fetch)
     _write(w, "WRITE_SIZE", write)
@@ -43,7 +46,10 @@ def test_pmc_summary_scales_by_the_copy_and_counts_timed_launches(tmp_path):
 
 
 def test_recorded_traffic_matches_committed_record():
-    """The committed Krylov record is found while its sources are unchanged."""
-    t = bench.recorded_traffic("krylov")
+    """The committed Krylov record is found for its own workload while its
+    sources are unchanged, and never for another workload or class."""
+    import workloads as W
+    t = bench.recorded_traffic("krylov", W.config(2).name)
     assert t is None or t > 0
-    assert bench.recorded_traffic("no_such_class") is None
+    assert bench.recorded_traffic("krylov", W.config(4).name) is None
+    assert bench.recorded_traffic("no_such_class", W.config(2).name) is None
