@@ -393,7 +393,7 @@ k_gtransfer(GArgs<T> a, int nrhs) {
 }
 
 // ---------------------------------------------------------------------------
-// coarsest level: e = Ainv f per slot (one wavefront per row)
+// coarsest level: e = Ainv f per slot (one workgroup per row)
 
 struct DenseArgs {
     int ns;
@@ -404,12 +404,15 @@ struct DenseArgs {
 template <class T, int RB>
 __global__ void __launch_bounds__(256)
 k_gdense(DenseArgs da, GArgs<T> a) {
+    // one row per workgroup: its 256 threads take the columns 256 apart
+    // (four row segments of 4 KB in flight per round), so even one block's
+    // ~1000 rows keep 16 wavefronts per compute unit reading the matrix
     const int slot = blockIdx.y;
     if (slot >= da.ns) return;
     const int N = da.N[slot];
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int row = blockIdx.x;
     if (row >= N) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const c128* A = da.Ainv[slot] + (int64_t)row * N;
     const cplx<T>* f = a.f[slot];
     cplx<T>* e = a.out[slot];
@@ -417,23 +420,22 @@ k_gdense(DenseArgs da, GArgs<T> a) {
     double accr[RB], acci[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) { accr[r] = 0.0; acci[r] = 0.0; }
-    // four row segments in flight per lane (the matrix read is the cost)
     constexpr int U = 4;
-    int c = lane;
-    for (; c + 64 * (U - 1) < N; c += 64 * U) {
+    int c = threadIdx.x;
+    for (; c + 256 * (U - 1) < N; c += 256 * U) {
         c128 av[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) av[u] = A[c + 64 * u];
+        for (int u = 0; u < U; ++u) av[u] = A[c + 256 * u];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                const cplx<T> fv = f[r * vf + c + 64 * u];
+                const cplx<T> fv = f[r * vf + c + 256 * u];
                 accr[r] += av[u].re * double(fv.re) - av[u].im * double(fv.im);
                 acci[r] += av[u].re * double(fv.im) + av[u].im * double(fv.re);
             }
     }
-    for (; c < N; c += 64) {
+    for (; c < N; c += 256) {
         const c128 av = A[c];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -442,13 +444,22 @@ k_gdense(DenseArgs da, GArgs<T> a) {
             acci[r] += av.re * double(fv.im) + av.im * double(fv.re);
         }
     }
+    // fixed-order reduction: within each wavefront, then over the four
+    __shared__ double sr[4][RB], si[4][RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
         for (int off = 32; off > 0; off >>= 1) {
             accr[r] += __shfl_xor(accr[r], off, 64);
             acci[r] += __shfl_xor(acci[r], off, 64);
         }
-        if (lane == 0) e[r * ve + row] = mk<T>(T(accr[r]), T(acci[r]));
+        if (lane == 0) { sr[wave][r] = accr[r]; si[wave][r] = acci[r]; }
+    }
+    __syncthreads();
+    if (threadIdx.x < RB) {
+        const int r = threadIdx.x;
+        const double re = (sr[0][r] + sr[1][r]) + (sr[2][r] + sr[3][r]);
+        const double im = (si[0][r] + si[1][r]) + (si[2][r] + si[3][r]);
+        e[r * ve + row] = mk<T>(T(re), T(im));
     }
 }
 

@@ -861,7 +861,7 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
                 a.vf[s] = vf[s];
                 a.vo[s] = vo[s];
             }
-            const dim3 g((unsigned)((Nmax + 3) / 4), (unsigned)ns);
+            const dim3 g((unsigned)Nmax, (unsigned)ns);        // one row per workgroup
             const int left = nrhs - r;
             if (left >= 8) { hipLaunchKernelGGL((k_gdense<T, 8>), g, dim3(256), 0, c->s, da, a); r += 8; }
             else if (left >= 4) { hipLaunchKernelGGL((k_gdense<T, 4>), g, dim3(256), 0, c->s, da, a); r += 4; }
