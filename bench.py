@@ -125,11 +125,11 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
     rec["source_sha256"] = sources_sha256(rec["source_files"])
     run = (f"python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp64 --roofline-kernel {kernel} "
            f"--copy-calibration")
+    fdir, wdir = os.path.dirname(fetch_csv), os.path.dirname(write_csv)
     rec["commands"] = [
-        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run -- {run}",
-        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run -- {run}",
-        f"python3 bench.py --roofline-kernel {kernel} --pmc-summary "
-        f"gpurun_out/pmc_fetch/run_counter_collection.csv gpurun_out/pmc_write/run_counter_collection.csv",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fdir} -o run -- {run}",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {wdir} -o run -- {run}",
+        f"python3 bench.py --roofline-kernel {kernel} --pmc-summary {fetch_csv} {write_csv}",
     ]
     return rec
 
@@ -179,8 +179,8 @@ def main():
                          indent=1))
         return
     if args.gpus != 1:
-        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this build "
-              "(sources would shard across GPUs with one all-reduce of the gradient at the end)",
+        print("bench.py: this solver runs on one GPU only; several GPUs would each take a share of "
+              "the sources, with one all-reduce of the gradient at the end",
               file=sys.stderr)
         sys.exit(2)
 
