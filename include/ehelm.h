@@ -75,6 +75,7 @@ typedef struct {
                                While a kernel class is timed (eh_timer_enable) plain launches are used. */
     int autotune;           /* 1: at the first solve / preconditioner call for a batch size, time every
                                candidate workgroup shape of the sweep, restriction and prolongation kernels
+                               (with fused legs: every tile configuration of each level's down and up leg)
                                per level and block group and keep the fastest (results are unchanged);
                                choices are cached in the file named by $EH_TUNE_CACHE when set */
     int fused;              /* 1: 2D V(1,nu_post) cycles (nu_post 1 or 2) from a zero guess run each level
