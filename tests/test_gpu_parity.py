@@ -377,7 +377,7 @@ def test_edge_cases():
 
 def test_preconditioner_and_solve_full_size_1024():
     """At the 1024 x 1024 benchmark size and settings (6 levels, V(1,2),
-    alpha 0.6): the FP64-multigrid preconditioner against the oracle's
+    alpha 0.7, FGMRES(4)): the FP64-multigrid preconditioner against the oracle's
     V-cycle preconditioner, and the complex64 solve's true residual
     recomputed by the oracle."""
     say("full-size preconditioner and solve 1024^2")
@@ -403,7 +403,7 @@ def test_preconditioner_and_solve_full_size_1024():
 
 def test_batched_solve_full_size_2048():
     """At the 2048 x 2048 batched size and settings (32 sources in one
-    multi-RHS solve, 7 levels, V(1,2), alpha 0.7, FGMRES(6), complex64
+    multi-RHS solve, 7 levels, V(1,2), alpha 0.7, FGMRES(4), complex64
     multigrid): every right-hand side converges, and the true residual of
     sampled right-hand sides, recomputed by the oracle from the GPU's
     solution, is below 1e-6."""

@@ -200,7 +200,7 @@ def config(k: int, scale: int = 1) -> Workload:
         src = [(1, (n[0] // 2, 1))]
         return Workload("config2_layered_1024", n, h, vp, vs, rho, omega,
                         abc_width=20, abc_sides=abc_all_but_top(2),
-                        sources=src, levels=6, alpha=0.6, restart=6)
+                        sources=src, levels=6, alpha=0.7, restart=4)
     if k == 3:
         n = (512 // scale, 512 // scale)
         vp, vs, rho = layered_medium(n, seed=1)
@@ -211,7 +211,7 @@ def config(k: int, scale: int = 1) -> Workload:
         return Workload("config3_fwi_512", n, h, vp, vs, rho, omega,
                         abc_width=20, abc_sides=abc_all_but_top(2),
                         sources=src, receivers=rec, levels=5, alpha=0.7,
-                        restart=6)
+                        restart=4)
     if k == 4:
         n = (2048 // scale, 2048 // scale)
         vp, vs, rho = layered_medium(n, seed=3, sigma_range=(0.25, 0.49))
@@ -220,7 +220,7 @@ def config(k: int, scale: int = 1) -> Workload:
         src = [(1, ((32 + 64 * s) // scale, 1)) for s in range(32)]
         return Workload("config4_layered_2048_b32", n, h, vp, vs, rho, omega,
                         abc_width=20, abc_sides=abc_all_but_top(2),
-                        sources=src, levels=7, alpha=0.7, restart=6)
+                        sources=src, levels=7, alpha=0.7, restart=4)
     if k == 5:
         n = (192 // scale,) * 3
         vp, vs, rho = layered_inclusion_medium_3d(n, seed=4)
