@@ -232,7 +232,7 @@ def config(k: int, scale: int = 1) -> Workload:
         return Workload("config5_layered_192cube", n, h, vp, vs, rho, omega,
                         abc_width=max(12 // scale, 1), abc_sides=abc_all_but_top(3),
                         sources=src, levels=5, nu=(2, 2),
-                        damping=(0.8, 0.8, 0.2), alpha=0.8, restart=6,
+                        damping=(0.8, 0.8, 0.2), alpha=1.0, restart=6,
                         intergrid="mixed")
     raise ValueError(f"unknown config {k}")
 
