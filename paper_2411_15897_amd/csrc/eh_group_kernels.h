@@ -175,13 +175,11 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
     const int64_t np = d.np();
     constexpr int NX = 2 * WX + 1, NY = 2 * WY + 1, NZ = 2 * WZ + 1;
     constexpr int NST = NX * NY * NZ;
-    constexpr int CENTRE = (WZ * NY + WY) * NX + WX;
     const cplx<T>* __restrict__ coef = a.coef[slot];
     const cplx<T>* __restrict__ dinv = a.dinv[slot];
     const cplx<T>* __restrict__ f = a.f[slot];
     cplx<T>* __restrict__ out = a.out[slot];
     const int64_t vf = a.vf[slot], vo = a.vo[slot];
-    const T damp = a.damp;
     const cplx<T> sc = dinv[p];
     if (MODE == 0) {
         for (int r = 0; r < nrhs; ++r) out[r * vo + p] = sc * f[r * vf + p];
