@@ -28,58 +28,112 @@ __device__ __forceinline__ int64_t face_cell(const Dims& dc, int kaxis, int i, i
     return ((int64_t)c[2] * dc.g[1] + c[1]) * dc.g[0] + c[0];
 }
 
-template <class Tin, int DIM>
+// Residual form (RES), for the FGMRES cycle starts: the launch writes
+// r = b - H x instead of H x and, per right-hand side, one partial sum of
+// |r|^2 per workgroup (a butterfly within each wavefront, then the four
+// wavefronts, in a fixed order), which k_reduce_partials adds up -- the
+// subtraction and the norm pass need not read the vectors again.
+// blockDim 256; every thread takes part in the sums, points outside the
+// field with zeros.
+struct ResArgs {
+    const c128* b;       // right-hand sides, same layout and stride as y
+    c128* partial;       // [rhs][workgroup]
+    int nblk;            // workgroups over all launches of one application
+    int blk0;            // first workgroup index of this launch
+};
+
+__device__ __forceinline__ void res_partial(const ResArgs& ra, int r, double v) {
+    __shared__ double sv[4];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) sv[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        const int blk = ra.blk0 + (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        ra.partial[(int64_t)r * ra.nblk + blk] = mk((sv[0] + sv[1]) + (sv[2] + sv[3]), 0.0);
+    }
+    __syncthreads();       // sv is reused by the next right-hand side
+}
+
+template <class Tin, int DIM, bool RES>
 __global__ void __launch_bounds__(256)
 k_op_face(Dims d, Dims dc, int kaxis, const double* __restrict__ w0, const double* __restrict__ w1,
           const double* __restrict__ w2, const c128* __restrict__ D0, const cplx<Tin>* __restrict__ u,
           const cplx<Tin>* __restrict__ pf, double ihk, c128* __restrict__ y, int nrhs,
-          int64_t vs_in, int64_t vs_out) {
-    EH_POINT_INDEX(d)
+          int64_t vs_in, int64_t vs_out, ResArgs ra) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    const bool in = i < d.g[0] && j < d.g[1];
+    if (!RES && !in) return;
+    const int64_t sy = d.g[0], sz = (int64_t)d.g[0] * d.g[1];
+    const int64_t p = k * sz + j * sy + i;
     FineCoef<double, 0, DIM> c;
-    c.load(d, i, j, k, p, w0, w1, w2, 0.0, 0.0, 0.0);
-    const c128 Dp = D0[p];
-    const int64_t chi = face_cell(dc, kaxis, i, j, k, 0);
-    const int64_t clo = face_cell(dc, kaxis, i, j, k, -1);
+    c128 Dp = mk(0.0, 0.0);
+    int64_t chi = -1, clo = -1;
+    if (in) {
+        c.load(d, i, j, k, p, w0, w1, w2, 0.0, 0.0, 0.0);
+        Dp = D0[p];
+        chi = face_cell(dc, kaxis, i, j, k, 0);
+        clo = face_cell(dc, kaxis, i, j, k, -1);
+    }
     for (int r = 0; r < nrhs; ++r) {
-        const cplx<Tin>* ur = u + r * vs_in;
-        const cplx<Tin>* pr = pf + r * vs_in;
-        // off-diagonal sum in FP64
-        c128 s = mk(0.0, 0.0);
-        if (i + 1 < d.g[0]) s = s + c.cp[0] * ccast<double>(ur[p + 1]);
-        if (i > 0) s = s + c.cm[0] * ccast<double>(ur[p - 1]);
-        if (j + 1 < d.g[1]) s = s + c.cp[1] * ccast<double>(ur[p + sy]);
-        if (j > 0) s = s + c.cm[1] * ccast<double>(ur[p - sy]);
-        if (DIM == 3) {
-            if (k + 1 < d.g[2]) s = s + c.cp[2] * ccast<double>(ur[p + sz]);
-            if (k > 0) s = s + c.cm[2] * ccast<double>(ur[p - sz]);
+        c128 yv = mk(0.0, 0.0);
+        if (in) {
+            const cplx<Tin>* ur = u + r * vs_in;
+            const cplx<Tin>* pr = pf + r * vs_in;
+            // off-diagonal sum in FP64
+            c128 s = mk(0.0, 0.0);
+            if (i + 1 < d.g[0]) s = s + c.cp[0] * ccast<double>(ur[p + 1]);
+            if (i > 0) s = s + c.cm[0] * ccast<double>(ur[p - 1]);
+            if (j + 1 < d.g[1]) s = s + c.cp[1] * ccast<double>(ur[p + sy]);
+            if (j > 0) s = s + c.cm[1] * ccast<double>(ur[p - sy]);
+            if (DIM == 3) {
+                if (k + 1 < d.g[2]) s = s + c.cp[2] * ccast<double>(ur[p + sz]);
+                if (k > 0) s = s + c.cm[2] * ccast<double>(ur[p - sz]);
+            }
+            c128 g = mk(0.0, 0.0);
+            if (chi >= 0) g = g + ccast<double>(pr[chi]);
+            if (clo >= 0) g = g - ccast<double>(pr[clo]);
+            yv = Dp * ccast<double>(ur[p]) - s + ihk * g;
+            if (RES) yv = ra.b[r * vs_out + p] - yv;
+            y[r * vs_out + p] = yv;
         }
-        c128 g = mk(0.0, 0.0);
-        if (chi >= 0) g = g + ccast<double>(pr[chi]);
-        if (clo >= 0) g = g - ccast<double>(pr[clo]);
-        y[r * vs_out + p] = Dp * ccast<double>(ur[p]) - s + ihk * g;
+        if (RES) res_partial(ra, r, yv.re * yv.re + yv.im * yv.im);
     }
 }
 
-template <class Tin, int DIM>
+template <class Tin, int DIM, bool RES>
 __global__ void __launch_bounds__(256)
 k_op_cell(Dims dc, const cplx<Tin>* __restrict__ u0, const cplx<Tin>* __restrict__ u1,
           const cplx<Tin>* __restrict__ u2, const cplx<Tin>* __restrict__ pf,
           const double* __restrict__ C, double ih0, double ih1, double ih2, c128* __restrict__ y,
-          int nrhs, int64_t vs_in, int64_t vs_out) {
-    EH_POINT_INDEX(dc)
+          int nrhs, int64_t vs_in, int64_t vs_out, ResArgs ra) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    const bool in = i < dc.g[0] && j < dc.g[1];
+    if (!RES && !in) return;
+    const int64_t p = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
     // face-grid strides: u0 grid (g0+1, g1, g2), u1 (g0, g1+1, g2), u2 (g0, g1, g2+1)
     const int64_t f0 = ((int64_t)k * dc.g[1] + j) * (dc.g[0] + 1) + i;
     const int64_t f1 = ((int64_t)k * (dc.g[1] + 1) + j) * dc.g[0] + i;
     const int64_t f2 = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
     const int64_t s2 = (int64_t)dc.g[0] * dc.g[1];
-    const double Cp = C[p];
+    const double Cp = in ? C[p] : 0.0;
     for (int r = 0; r < nrhs; ++r) {
-        const int64_t o = r * vs_in;
-        c128 div = ih0 * (ccast<double>(u0[o + f0 + 1]) - ccast<double>(u0[o + f0]));
-        div = div + ih1 * (ccast<double>(u1[o + f1 + dc.g[0]]) - ccast<double>(u1[o + f1]));
-        if (DIM == 3) div = div + ih2 * (ccast<double>(u2[o + f2 + s2]) - ccast<double>(u2[o + f2]));
-        const c128 pv = ccast<double>(pf[o + p]);
-        y[r * vs_out + p] = mk(-div.re - Cp * pv.re, -div.im - Cp * pv.im);
+        c128 yv = mk(0.0, 0.0);
+        if (in) {
+            const int64_t o = r * vs_in;
+            c128 div = ih0 * (ccast<double>(u0[o + f0 + 1]) - ccast<double>(u0[o + f0]));
+            div = div + ih1 * (ccast<double>(u1[o + f1 + dc.g[0]]) - ccast<double>(u1[o + f1]));
+            if (DIM == 3) div = div + ih2 * (ccast<double>(u2[o + f2 + s2]) - ccast<double>(u2[o + f2]));
+            const c128 pv = ccast<double>(pf[o + p]);
+            yv = mk(-div.re - Cp * pv.re, -div.im - Cp * pv.im);
+            if (RES) yv = ra.b[r * vs_out + p] - yv;
+            y[r * vs_out + p] = yv;
+        }
+        if (RES) res_partial(ra, r, yv.re * yv.re + yv.im * yv.im);
     }
 }
 

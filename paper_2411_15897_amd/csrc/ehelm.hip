@@ -148,6 +148,7 @@ struct eh_ctx {
     void* Z = nullptr;            // m * nrhs * ndof, multigrid precision
     c128* W = nullptr;            // nrhs * ndof
     c128* partial = nullptr;
+    c128* res_partial = nullptr;    // [rhs][workgroups of one operator application]
     c128* dsmall = nullptr;       // small device arrays (coefs, results)
     int kry_nblk = 0;
     // device-side Arnoldi state and the host-visible status records
@@ -1235,34 +1236,72 @@ void maybe_autotune(eh_ctx* c, int nrhs) {
 // ---------------------------------------------------------------------------
 // operator and preconditioner
 
+template <class Tin, bool RES>
+void launch_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs, ResArgs ra) {
+    const cplx<Tin>* X = (const cplx<Tin>*)x;
+    const cplx<Tin>* pf = X + c->off[c->dim];
+    const c128* b = ra.b;
+    for (int k = 0; k < c->dim; ++k) {
+        const Dims& d = c->dface[k];
+        const dim3 g = grid_of(d);
+        ra.b = RES ? b + c->off[k] : nullptr;
+        if (c->dim == 2)
+            hipLaunchKernelGGL((k_op_face<Tin, 2, RES>), g, kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
+                               c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
+                               y + c->off[k], nrhs, vx, vy, ra);
+        else
+            hipLaunchKernelGGL((k_op_face<Tin, 3, RES>), g, kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
+                               c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
+                               y + c->off[k], nrhs, vx, vy, ra);
+        HIPCHK(hipGetLastError());
+        ra.blk0 += (int)(g.x * g.y * g.z);
+    }
+    const cplx<Tin>* u2 = c->dim == 3 ? X + c->off[2] : X;
+    ra.b = RES ? b + c->off[c->dim] : nullptr;
+    if (c->dim == 2)
+        hipLaunchKernelGGL((k_op_cell<Tin, 2, RES>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, X + c->off[0],
+                           X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
+                           y + c->off[c->dim], nrhs, vx, vy, ra);
+    else
+        hipLaunchKernelGGL((k_op_cell<Tin, 3, RES>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, X + c->off[0],
+                           X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
+                           y + c->off[c->dim], nrhs, vx, vy, ra);
+    HIPCHK(hipGetLastError());
+}
+
+// workgroups of one operator application (the face grids and the cells)
+inline int op_blocks(const eh_ctx* c) {
+    int nb = 0;
+    for (int k = 0; k < c->dim; ++k) {
+        const dim3 g = grid_of(c->dface[k]);
+        nb += (int)(g.x * g.y * g.z);
+    }
+    const dim3 g = grid_of(c->dcell);
+    return nb + (int)(g.x * g.y * g.z);
+}
+
 template <class Tin>
 void apply_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs) {
-    const cplx<Tin>* X = (const cplx<Tin>*)x;
     double coefb = 8.0 * c->ncell;
     for (int k = 0; k < c->dim; ++k) coefb += (double)c->fsize[k] * (8.0 * c->dim + 16.0);
     Timed tm(c, KC_OPERATOR, coefb + (double)nrhs * c->ndof * (sizeof(cplx<Tin>) + sizeof(c128)));
-    const cplx<Tin>* pf = X + c->off[c->dim];
-    for (int k = 0; k < c->dim; ++k) {
-        const Dims& d = c->dface[k];
-        if (c->dim == 2)
-            hipLaunchKernelGGL((k_op_face<Tin, 2>), grid_of(d), kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
-                               c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
-                               y + c->off[k], nrhs, vx, vy);
-        else
-            hipLaunchKernelGGL((k_op_face<Tin, 3>), grid_of(d), kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
-                               c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
-                               y + c->off[k], nrhs, vx, vy);
-        HIPCHK(hipGetLastError());
-    }
-    const cplx<Tin>* u2 = c->dim == 3 ? X + c->off[2] : X;
-    if (c->dim == 2)
-        hipLaunchKernelGGL((k_op_cell<Tin, 2>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, X + c->off[0],
-                           X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
-                           y + c->off[c->dim], nrhs, vx, vy);
-    else
-        hipLaunchKernelGGL((k_op_cell<Tin, 3>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, X + c->off[0],
-                           X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
-                           y + c->off[c->dim], nrhs, vx, vy);
+    launch_H<Tin, false>(c, x, vx, y, vy, nrhs, ResArgs{});
+}
+
+// r = b - H x for nrhs complex128 vectors of stride ndof, and nrm[q] =
+// |r_q|^2 (the cycle start of FGMRES) from the same launches.
+void residual_H(eh_ctx* c, const c128* x, const c128* b, c128* r, int nrhs, c128* nrm) {
+    const int nb = op_blocks(c);
+    double coefb = 8.0 * c->ncell;
+    for (int k = 0; k < c->dim; ++k) coefb += (double)c->fsize[k] * (8.0 * c->dim + 16.0);
+    Timed tm(c, KC_OPERATOR, coefb + (double)nrhs * c->ndof * 3.0 * sizeof(c128));
+    ResArgs ra{};
+    ra.b = b;
+    ra.partial = c->res_partial;
+    ra.nblk = nb;
+    ra.blk0 = 0;
+    launch_H<double, true>(c, x, c->ndof, r, c->ndof, nrhs, ra);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1, nrhs), dim3(256), 0, c->s, nb, 1, nrhs, c->res_partial, nrm);
     HIPCHK(hipGetLastError());
 }
 
@@ -1361,7 +1400,7 @@ void ensure_krylov(eh_ctx* c, int nrhs, int m) {
     if (nrhs <= c->kry_nrhs && m <= c->kry_m) return;
     HIPCHK(hipStreamSynchronize(c->s));
     drop_graphs(c);
-    c->release(c->V); c->release(c->Z); c->release(c->W); c->release(c->partial);
+    c->release(c->V); c->release(c->Z); c->release(c->W); c->release(c->partial); c->release(c->res_partial);
     c->release(c->dsmall);
     c->release(c->arn.sv);
     free_arn_status(c);
@@ -1370,6 +1409,7 @@ void ensure_krylov(eh_ctx* c, int nrhs, int m) {
     c->W = c->alloc<c128>((size_t)nrhs * c->ndof);
     c->kry_nblk = (int)std::max<int64_t>(1, (c->ndof + KRY_E * KRY_THREADS - 1) / (KRY_E * KRY_THREADS));
     c->partial = c->alloc<c128>((size_t)c->kry_nblk * nrhs * 2 * (m + 1));
+    c->res_partial = c->alloc<c128>((size_t)op_blocks(c) * nrhs);
     c->dsmall = c->alloc<c128>((size_t)6 * nrhs * (m + 2));
     // Arnoldi state: one allocation carved into 16-byte aligned arrays
     const size_t R = nrhs, M = m;
@@ -1448,9 +1488,9 @@ void gs_pass(eh_ctx* c, int64_t n, int m, int nrhs, const c128* V, const c128* w
 //   prec(v, sv, z_j)  z_j = M (sv[q * (m+1)] v) per right-hand side q
 // with vectors of length n, right-hand side q at offset q * n.  Graph
 // capture is used only for the full system (`graphs`).
-template <class T, class OpX, class OpZ, class Prec>
+template <class T, class OpX, class OpZ, class Prec, class OpRes>
 eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool graphs, const c128* b, c128* x,
-                      int nrhs, double tol, int maxit, eh_info* info) {
+                      int nrhs, double tol, int maxit, eh_info* info, OpRes op_res) {
     const int m = c->o.restart;
     const int64_t vstep = (int64_t)nrhs * n;    // distance between basis vectors
     cplx<T>* Z = (cplx<T>*)c->Z;
@@ -1481,12 +1521,15 @@ eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool 
         // r = b - H x into stored column 0; its norm starts the cycle
         if (first) {
             HIPCHK(hipMemcpyAsync(c->V, b, (size_t)vstep * sizeof(c128), hipMemcpyDeviceToDevice, c->s));
-        } else {
+            gs_pass<3>(c, n, 1, nrhs, nullptr, c->V, nullptr, d3);
+        } else if (!op_res(x, c->V, d3)) {
+            // (op_res: r and |r|^2 from the operator launch itself, where the
+            // problem provides it)
             op_x(x, c->W);
             hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, b, c->W, c->V);
             HIPCHK(hipGetLastError());
+            gs_pass<3>(c, n, 1, nrhs, nullptr, c->V, nullptr, d3);
         }
-        gs_pass<3>(c, n, 1, nrhs, nullptr, c->V, nullptr, d3);
         hipLaunchKernelGGL(k_arn_start, dim3(rgrid), dim3(64), 0, c->s, S, (const c128*)d3, first ? 1 : 0, tol,
                            ds + (size_t)m * nrhs);
         HIPCHK(hipGetLastError());
@@ -1596,8 +1639,12 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
     const int m = c->o.restart;
     auto op_x = [&](const c128* xx, c128* w) { apply_H<double>(c, xx, n, w, n, nrhs); };
     auto op_z = [&](const cplx<T>* z, c128* w) { apply_H<T>(c, z, n, w, n, nrhs); };
+    auto op_res = [&](const c128* xx, c128* r, c128* nrm) {
+        residual_H(c, xx, b, r, nrhs, nrm);
+        return true;
+    };
     auto prec = [&](const c128* v, const double* sv, cplx<T>* z) { apply_M<T>(c, v, n, z, n, nrhs, sv, m + 1); };
-    return fgmres_core<T>(c, n, op_x, op_z, prec, c->o.graphs != 0, b, x, nrhs, tol, maxit, info);
+    return fgmres_core<T>(c, n, op_x, op_z, prec, c->o.graphs != 0, b, x, nrhs, tol, maxit, info, op_res);
 }
 
 eh_status fail(eh_ctx* c, eh_status st, const std::string& msg);
@@ -1643,7 +1690,8 @@ eh_status block_solve_impl(eh_ctx* c, int block, const c128* f, c128* x, int nrh
         void* out[1] = {z};
         gcycle<T>(c, kinds, 1, 0, fa, vf, out, vf, false, nrhs);
     };
-    return fgmres_core<T>(c, n, op_x, op_z, prec, false, f, x, nrhs, tol, maxit, info);
+    auto no_res = [](const c128*, c128*, c128*) { return false; };
+    return fgmres_core<T>(c, n, op_x, op_z, prec, false, f, x, nrhs, tol, maxit, info, no_res);
 }
 
 void ensure_zbuf(eh_ctx* c) {
