@@ -5,8 +5,10 @@ block-acoustic preconditioner with one multigrid V-cycle per block) of the
 1024 x 1024 layered + random medium with one top point source, with all
 inputs resident in HBM.  The headline form is the complex64 multigrid under
 FP64 FGMRES; the plain FP64 form is timed beside it.  The line also carries
-the roofline figure of the dominant kernel (event-timed inside the timed
-region) and the CPU oracle's rate on a bounded sample.
+the roofline figure of the V-cycle kernels, which take most of the solve
+(every multigrid launch event-timed over the timed solves: algorithmic
+bytes over launch time against the HBM peak), the per-class split of one
+solve, and the CPU oracle's rate on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -62,6 +64,13 @@ def cpu_baseline(wl, iters_ref, n_iters):
     }
 
 
+# the multigrid cycles proper (smoothing, residuals, transfers, coarsest
+# solve), as opposed to the operator, the distributor, the coupling and the
+# Krylov passes around them: the event-timer classes of the "vcycle" group
+VCYCLE_CLASSES = ("fine_first", "fine_sweep", "fine_resid", "fine_down", "fine_up", "coarse", "coarse_down",
+                  "coarse_up", "restrict", "prolong", "dense")
+TIMER_GROUPS = {"vcycle": VCYCLE_CLASSES}
+
 # Kernels of each event-timer class (substrings of the demangled names
 # rocprofv3 prints) and, where a timed launch spans several dispatches, the
 # ones that open a timed launch (a Gram-Schmidt pass is k_gs plus its
@@ -73,10 +82,13 @@ CLASS_KERNELS = {
     "coarse_down": (("eh::k_fdown<float, false", "eh::k_fdown<double, false"), None),
     "coarse_up": (("eh::k_fup<float, false", "eh::k_fup<double, false"), None),
     "coarse": (("eh::k_gstencil<",), None),
-    "operator": (("eh::k_op_face<", "eh::k_op_cell<"), None),
+    "operator": (("eh::k_op_face<", "eh::k_op_cell<"), ("eh::k_op_cell<",)),   # one H apply = 3 (4) fields
     "distribute": (("eh::k_distribute<",), None),
     "couple": (("eh::k_gcouple<",), None),
     "dense": (("eh::k_gdense<",), None),
+    # every timed multigrid kernel: the V-cycles of the three (four) blocks
+    "vcycle": (("eh::k_fdown<", "eh::k_fup<", "eh::k_gdense<", "eh::k_gstencil<", "eh::k_gfine<",
+                "eh::k_gtransfer<"), None),
 }
 CLASS_SOURCES = {
     "krylov": ["paper_2411_15897_amd/csrc/eh_krylov_kernels.h", "paper_2411_15897_amd/csrc/eh_common.h"],
@@ -84,6 +96,35 @@ CLASS_SOURCES = {
 DEFAULT_SOURCES = ["paper_2411_15897_amd/csrc/eh_fused_kernels.h", "paper_2411_15897_amd/csrc/eh_group_kernels.h",
                    "paper_2411_15897_amd/csrc/eh_mg_kernels.h", "paper_2411_15897_amd/csrc/eh_op_kernels.h",
                    "paper_2411_15897_amd/csrc/eh_common.h"]
+
+
+
+
+def timer_classes(kernel):
+    """The event-timer classes of a class name or a group name."""
+    from paper_2411_15897_amd._native import KERNEL_CLASSES
+    names = TIMER_GROUPS.get(kernel, (kernel,))
+    bad = [k for k in names if k not in KERNEL_CLASSES]
+    if bad:
+        raise SystemExit(f"bench.py: unknown kernel class {bad}")
+    return list(names)
+
+
+def vcycle_summary(split_bytes):
+    """Algorithmic GB/s of all V-cycle launches of one event-timed solve
+    (sum of bytes / sum of launch durations) against the HBM peak, and the
+    V-cycles' share of the event-timed solve."""
+    if not split_bytes:
+        return None
+    ms = sum(split_bytes[k][0] for k in VCYCLE_CLASSES if k in split_bytes)
+    nbytes = sum(split_bytes[k][1] for k in VCYCLE_CLASSES if k in split_bytes)
+    total = sum(v[0] for v in split_bytes.values())
+    if ms <= 0:
+        return None
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"classes": [k for k in VCYCLE_CLASSES if k in split_bytes], "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "ms_one_solve": round(ms, 3),
+            "share_of_solve": ms / total}
 
 
 def sources_sha256(files):
@@ -98,7 +139,10 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
     """HBM traffic per timed launch of a kernel class from a FETCH_SIZE and a
     WRITE_SIZE rocprofv3 counter run (KiB per dispatch), each scaled by what
     the same counter reads for the 1 GiB calibration copy of the same run
-    (the run's first copy dispatch: it precedes the solver's own copies)."""
+    (the run's first copy dispatch: it precedes the solver's own copies).
+    Only the run's last solve counts: the dispatches after the last copy
+    (each solve starts by copying b into the first basis column and copies
+    nothing else), so set-up and tuning launches do not enter."""
     import csv
     members, leads = CLASS_KERNELS[kernel]
     leads = leads or members
@@ -110,7 +154,8 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
                         if "__amd_rocclr_copyBuffer" in r["Kernel_Name"])
         ref = copies[0][1]                              # the 1 GiB calibration copy
         scale = (1 << 30) / 1024.0 / ref
-        cls = [r for r in rows if any(m in r["Kernel_Name"] for m in members)]
+        last = copies[-1][0]                            # start of the last solve
+        cls = [r for r in rows if int(r["Dispatch_Id"]) > last and any(m in r["Kernel_Name"] for m in members)]
         nlaunch = sum(1 for r in cls if any(m in r["Kernel_Name"] for m in leads))
         kib = sum(float(r["Counter_Value"]) for r in cls) / max(nlaunch, 1)
         rec[f"{tag}_kib_per_launch_raw"] = kib
@@ -120,11 +165,11 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
         rec[f"dispatches_{tag}"] = len(cls)
         total += kib * scale * 1024.0
     rec["copy_reference"] = "torch copy of 1 GiB (__amd_rocclr_copyBuffer) in the same runs"
+    rec["launches_counted"] = "the dispatches of the run's last solve (after its last copy)"
     rec["traffic_bytes_per_launch"] = total
     rec["source_files"] = CLASS_SOURCES.get(kernel, DEFAULT_SOURCES)
     rec["source_sha256"] = sources_sha256(rec["source_files"])
-    run = (f"python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp64 --roofline-kernel {kernel} "
-           f"--copy-calibration")
+    run = "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp64 --copy-calibration"
     fdir, wdir = os.path.dirname(fetch_csv), os.path.dirname(write_csv)
     rec["commands"] = [
         f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fdir} -o run -- {run}",
@@ -132,6 +177,28 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
         f"python3 bench.py --roofline-kernel {kernel} --pmc-summary {fetch_csv} {write_csv}",
     ]
     return rec
+
+
+def trace_summary(trace_csv, solves):
+    """Per kernel class (and the vcycle group): launches and average
+    duration over the last `solves` solves of a rocprofv3 --kernel-trace
+    run of this script with --no-fp64 --no-cpu-baseline (its last solves
+    are the event-timed ones; each solve starts with its one copy)."""
+    import csv
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
+    copies = [i for i, r in enumerate(rows) if "__amd_rocclr_copyBuffer" in r["Kernel_Name"]]
+    tail = rows[copies[-solves] + 1:]
+    out = {}
+    for k, (members, leads) in CLASS_KERNELS.items():
+        leads = leads or members
+        sel = [r for r in tail if any(m in r["Kernel_Name"] for m in members)]
+        if not sel:
+            continue
+        n = sum(1 for r in sel if any(m in r["Kernel_Name"] for m in leads))
+        ns = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in sel)
+        out[k] = {"dispatches": len(sel), "launches": n, "total_ms": ns * 1e-6,
+                  "avg_us": ns * 1e-3 / max(n, 1)}
+    return out
 
 
 def recorded_traffic(kernel, workload):
@@ -162,17 +229,23 @@ def main():
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--restart", type=int, default=None)
-    ap.add_argument("--roofline-kernel", default="auto",
-                    help="kernel class for the roofline figure; auto = the class with the most time")
+    ap.add_argument("--roofline-kernel", default="vcycle",
+                    help="kernel class (or the group vcycle: every multigrid kernel) for the roofline figure")
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB with torch before the solves (reference dispatch for HBM counters)")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="no GPU work: per-class launches and average durations over the last --steps solves "
+                         "of a rocprofv3 --kernel-trace run of this script (--no-fp64 --no-cpu-baseline)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: print the HBM traffic record of --roofline-kernel from the counter "
                          "CSVs of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary, args.steps), indent=1))
+        return
     if args.pmc_summary:
         import workloads as W
         print(json.dumps(pmc_summary(*args.pmc_summary, args.roofline_kernel, W.config(args.config).name),
@@ -211,9 +284,11 @@ def main():
         for w in range(warmup):
             _, info = solver.solve(b, tol=wl.tol, maxit=5000)
             log(f"warmup {w}: iters {info[0]['iters']} relres {info[0]['relres_true']:.2e}")
-        if kernel:
-            solver.timer_read(kernel)          # drop anything recorded before
-            solver.timer_enable([kernel])
+        classes = timer_classes(kernel) if kernel else []
+        for k in classes:
+            solver.timer_read(k)               # drop anything recorded before
+        if classes:
+            solver.timer_enable(classes)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         infos = []
@@ -222,7 +297,10 @@ def main():
             infos.append(info)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        kt = solver.timer_read(kernel) if kernel else None
+        kt = None
+        if classes:
+            reads = [solver.timer_read(k) for k in classes]
+            kt = tuple(sum(r[i] for r in reads) for i in range(3))
         solver.timer_enable([])
         log(f"timed {steps} solves in {dt:.3f} s, iters {[i[0]['iters'] for i in infos]}")
         return dt, infos, kt
@@ -240,26 +318,26 @@ def main():
     log(f"setup (complex64 multigrid) {time.perf_counter() - t_setup:.2f} s")
     kernel = args.roofline_kernel
     split = {}
-    if kernel == "auto":
-        # one untimed solve with every kernel class event-timed picks the
-        # class that takes the most time
-        from paper_2411_15897_amd._native import KERNEL_CLASSES
-        s32.timer_enable(list(KERNEL_CLASSES))
-        s32.solve(b, tol=wl.tol, maxit=5000)
-        for k in KERNEL_CLASSES:
-            n_, ms_, by_ = s32.timer_read(k)
-            if n_:
-                split[k] = {"launches": n_, "ms": round(ms_, 3),
-                            "GB_s": round(by_ / (ms_ * 1e-3) / 1e9, 1)}
-        s32.timer_enable([])
-        kernel = max(split, key=lambda k: split[k]["ms"])
-        log(f"per-class split of one solve: {json.dumps(split)}")
-        log(f"dominant kernel class: {kernel}")
+    split_bytes = {}
+    # one untimed solve with every kernel class event-timed: the split of
+    # the solve over the classes
+    from paper_2411_15897_amd._native import KERNEL_CLASSES
+    s32.timer_enable(list(KERNEL_CLASSES))
+    s32.solve(b, tol=wl.tol, maxit=5000)
+    for k in KERNEL_CLASSES:
+        n_, ms_, by_ = s32.timer_read(k)
+        if n_:
+            split[k] = {"launches": n_, "ms": round(ms_, 3),
+                        "GB_s": round(by_ / (ms_ * 1e-3) / 1e9, 1)}
+            split_bytes[k] = (ms_, by_)
+    s32.timer_enable([])
+    log(f"per-class split of one solve: {json.dumps(split)}")
     # value: the solve as it runs (Arnoldi steps replayed from HIP graphs)
     dt32, inf32, _ = timed(s32, args.steps, args.warmup, None)
-    # roofline: the same K solves again with the dominant kernel class
-    # bracketed by HIP events on the solver's stream (plain launches; the
-    # kernels are the same, only the launch path differs)
+    # roofline: the same K solves again with every launch of the roofline
+    # class (default: all V-cycle kernels) bracketed by HIP events on the
+    # solver's stream (plain launches; the kernels are the same, only the
+    # launch path differs)
     _, _, kt = timed(s32, args.steps, 0, kernel)
     it32 = inf32[-1][0]["iters"]
     rel32 = max(i[0]["relres_true"] for i in inf32)
@@ -328,6 +406,7 @@ def main():
         "fp64_plain": fp64,
         "roofline": roof,
         "kernel_split_one_solve": split or None,
+        "vcycle_one_solve": vcycle_summary(split_bytes),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

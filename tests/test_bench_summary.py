@@ -1,8 +1,9 @@
-"""bench.py's counter summariser on a small synthetic counter file (no GPU):
-the 1 GiB calibration copy (the run's first copy, not a later larger one)
-fixes the scale of each counter, dispatches of a
-class are summed and divided by its timed launches (a Gram-Schmidt pass is
-two dispatches), and the record carries the hash of the kernel sources."""
+"""bench.py's counter and trace summarisers on small synthetic files (no
+GPU): the 1 GiB calibration copy (the run's first copy, not a later larger
+one) fixes the scale of each counter, only the last solve's dispatches of a
+class (after the run's last copy) are summed and divided by its timed
+launches (a Gram-Schmidt pass is two dispatches), and the record carries
+the hash of the kernel sources."""
 import csv
 import os
 
@@ -21,16 +22,25 @@ def _write(path, counter, rows):
 
 def test_pmc_summary_scales_by_the_copy_and_counts_timed_launches(tmp_path):
     gib_kib = (1 << 30) / 1024.0
+    tune = ("void eh::k_fup<float, true, 2, 1>(eh::GArgs<float>, int)", 7777.0)   # set-up / tuning
     fetch = [("__amd_rocclr_copyBuffer", gib_kib / 2),          # the counter reads half
+             tune,
+             ("__amd_rocclr_copyBuffer", gib_kib),               # an earlier solve starts
+             ("void eh::k_gs<4>(long, int)", 3000.0), tune,
+             ("__amd_rocclr_copyBuffer", 2 * gib_kib),           # the last solve starts (larger copy)
              ("void eh::k_gs<4>(long, int)", 1000.0), ("eh::k_reduce_partials(int)", 10.0),
              ("void eh::k_gs<2>(long, int)", 2000.0), ("eh::k_reduce_partials(int)", 10.0),
              ("void eh::k_fup<float, true, 2, 0>(eh::GArgs<float>, int)", 5000.0),
-             ("__amd_rocclr_copyBuffer", gib_kib)]                # a later, larger copy of the solver
+             ("void eh::k_gdense<float, 1>(eh::DenseArgs, eh::GArgs<float>)", 300.0)]
     write = [("__amd_rocclr_copyBuffer", gib_kib),
+             tune,
+             ("__amd_rocclr_copyBuffer", gib_kib),
+             ("void eh::k_gs<4>(long, int)", 3000.0), tune,
+             ("__amd_rocclr_copyBuffer", 2 * gib_kib),
              ("void eh::k_gs<4>(long, int)", 0.0), ("eh::k_reduce_partials(int)", 1.0),
              ("void eh::k_gs<2>(long, int)", 500.0), ("eh::k_reduce_partials(int)", 1.0),
              ("void eh::k_fup<float, true, 2, 0>(eh::GArgs<float>, int)", 900.0),
-             ("__amd_rocclr_copyBuffer", 2 * gib_kib)]
+             ("void eh::k_gdense<float, 1>(eh::DenseArgs, eh::GArgs<float>)", 100.0)]
     f, w = tmp_path / "fetch.csv", tmp_path / "write.csv"
     _write(f, "FETCH_SIZE", fetch)
     _write(w, "WRITE_SIZE", write)
@@ -43,6 +53,34 @@ def test_pmc_summary_scales_by_the_copy_and_counts_timed_launches(tmp_path):
     up = bench.pmc_summary(str(f), str(w), "fine_up", "test")
     assert up["launches_fetch"] == 1
     assert abs(up["traffic_bytes_per_launch"] - (5000 * 2.0 + 900) * 1024.0) < 1e-6
+    vc = bench.pmc_summary(str(f), str(w), "vcycle", "test")
+    assert vc["launches_fetch"] == 2 and vc["launches_write"] == 2
+    assert abs(vc["traffic_bytes_per_launch"] - ((5000 + 300) * 2.0 + 900 + 100) / 2 * 1024.0) < 1e-6
+
+
+def test_trace_summary_counts_the_last_solves(tmp_path):
+    """Launch counts and mean durations over the last K solves of a kernel
+    trace (each solve opens with its copy; earlier launches are ignored)."""
+    import csv as _csv
+    rows = [("__amd_rocclr_copyBuffer", 5), ("void eh::k_fup<float, true, 2, 1>(x)", 999),
+            ("__amd_rocclr_copyBuffer", 5), ("void eh::k_fup<float, true, 2, 0>(x)", 20),
+            ("void eh::k_gs<4>(long, int)", 30), ("eh::k_reduce_partials(int)", 4),
+            ("__amd_rocclr_copyBuffer", 5), ("void eh::k_fup<float, false, 2, 0>(x)", 10),
+            ("void eh::k_fdown<float, true, 1>(x)", 12)]
+    path = tmp_path / "trace.csv"
+    with open(path, "w", newline="") as fp:
+        wr = _csv.DictWriter(fp, fieldnames=["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        wr.writeheader()
+        t = 1000
+        for i, (name, us) in enumerate(rows):
+            wr.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Start_Timestamp": t,
+                         "End_Timestamp": t + us * 1000})
+            t += us * 1000 + 500
+    out = bench.trace_summary(str(path), 2)
+    assert out["vcycle"]["launches"] == 3
+    assert abs(out["vcycle"]["avg_us"] - (20 + 10 + 12) / 3) < 1e-9
+    assert out["krylov"]["launches"] == 1 and abs(out["krylov"]["avg_us"] - 34) < 1e-9
+    assert out["fine_up"]["launches"] == 1 and out["coarse_up"]["launches"] == 1
 
 
 def test_recorded_traffic_matches_committed_record():
@@ -53,3 +91,17 @@ def test_recorded_traffic_matches_committed_record():
     assert t is None or t > 0
     assert bench.recorded_traffic("krylov", W.config(4).name) is None
     assert bench.recorded_traffic("no_such_class", W.config(2).name) is None
+
+
+def test_vcycle_summary_sums_bytes_and_time_of_the_multigrid_classes():
+    """The V-cycle figure is total bytes over total duration of the multigrid
+    classes only (not an average of their rates); the operator and Krylov
+    classes count only in the share of the solve."""
+    split = {"fine_down": (2.0, 6e9 * 2e-3), "coarse_up": (6.0, 1e9 * 6e-3), "dense": (1.0, 3e9 * 1e-3),
+             "krylov": (4.0, 5e9 * 4e-3), "operator": (3.0, 4e9 * 3e-3)}
+    v = bench.vcycle_summary(split)
+    assert v["classes"] == ["fine_down", "coarse_up", "dense"]
+    assert abs(v["achieved"] - (12e6 + 6e6 + 3e6) / 9e-3 / 1e9) < 0.05
+    assert abs(v["frac"] - v["achieved"] / bench.HBM_PEAK_GBS) < 1e-5
+    assert abs(v["share_of_solve"] - 9.0 / 16.0) < 1e-12
+    assert bench.vcycle_summary({}) is None
