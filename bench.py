@@ -152,6 +152,9 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         copies = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows
                         if "__amd_rocclr_copyBuffer" in r["Kernel_Name"])
+        if len(copies) < 2:
+            raise SystemExit(f"bench.py: {path} holds {len(copies)} copy dispatches; a run with "
+                             "--copy-calibration and at least one solve has two or more")
         ref = copies[0][1]                              # the 1 GiB calibration copy
         scale = (1 << 30) / 1024.0 / ref
         last = copies[-1][0]                            # start of the last solve
@@ -187,6 +190,9 @@ def trace_summary(trace_csv, solves):
     import csv
     rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
     copies = [i for i, r in enumerate(rows) if "__amd_rocclr_copyBuffer" in r["Kernel_Name"]]
+    if solves < 1 or len(copies) < solves:
+        raise SystemExit(f"bench.py: {trace_csv} holds {len(copies)} solves (copy dispatches), "
+                         f"fewer than --steps {solves}")
     tail = rows[copies[-solves] + 1:]
     out = {}
     for k, (members, leads) in CLASS_KERNELS.items():
