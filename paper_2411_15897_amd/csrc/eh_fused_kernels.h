@@ -27,7 +27,11 @@
 // the stencil sums need no bounds tests.
 //
 // Launch: blockDim (threads of the tile configuration, 1D), gridDim (tiles
-// x, tiles y, slots of the group).
+// x, tiles y, slots of the group x chunks of right-hand sides): workgroup
+// z handles slot z % ns and right-hand sides [c * rch, min(nrhs, c * rch +
+// rch)) with c = z / ns, one after the other.  Splitting a batch over
+// workgroups only changes which workgroup computes a right-hand side, not
+// its arithmetic.
 #pragma once
 
 #include "eh_common.h"
@@ -143,7 +147,7 @@ struct PointOp {
 // down leg: a.d = level l, a.dc = level l+1, a.f = f_l (vf), a.out = f_{l+1} (vo)
 
 template <class T, bool FINE, int KIND, int WX, int WY, int NM, bool MIXED, int CX, int CY, int NT>
-__device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* lds, int nrhs, int tile_x,
+__device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* lds, int r0, int r1, int tile_x,
                                           int tile_y) {
     const Dims d = a.d[slot], dc = a.dc[slot];
     const int X0 = tile_x * CX, Y0 = tile_y * CY;
@@ -166,10 +170,10 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
     const int64_t rp = (int64_t)mgy * nx + mgx;
     PointOp<T, FINE, KIND, WX, WY, !FINE && NM != 0 && !MIXED> rop;
     if (rin) rop.load(a, slot, d, mgx, mgy, rp);
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = r0; r < r1; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
         const cplx<T> fr = rin ? f[rp] : czero<T>();
-        if (r > 0) __syncthreads();                 // LDS of the previous RHS consumed
+        if (r > r0) __syncthreads();                // LDS of the previous RHS consumed
 #pragma unroll 1
         for (int it = 0; it < (UX * UY + NT - 1) / NT; ++it) {
             const int q = threadIdx.x + it * NT;
@@ -230,15 +234,15 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
 
 template <class T, bool FINE, int CFG>
 __global__ void __launch_bounds__(kFDown[CFG].threads)
-k_fdown(GArgs<T> a, int nrhs) {
+k_fdown(GArgs<T> a, int nrhs, int rch) {
     constexpr int CX = kFDown[CFG].x, CY = kFDown[CFG].y, NT = kFDown[CFG].threads;
     __shared__ cplx<T> lds[fd_lds(CX, CY)];
-    const int slot = blockIdx.z;
-    if (slot >= a.ns) return;
+    const int slot = blockIdx.z % a.ns;
+    const int r0 = (blockIdx.z / a.ns) * rch, r1 = min(nrhs, r0 + rch);
     const int kind = a.kind[slot];           // 0: A_1, 1: A_2, 2: H_p
     int tx, ty;
     xcd_tile(tx, ty);
-#define EH_FD(FI, KI, WX, WY, NM, MX) down_body<T, FI, KI, WX, WY, NM, MX, CX, CY, NT>(a, slot, lds, nrhs, tx, ty)
+#define EH_FD(FI, KI, WX, WY, NM, MX) down_body<T, FI, KI, WX, WY, NM, MX, CX, CY, NT>(a, slot, lds, r0, r1, tx, ty)
     if (FINE && kind == 2 && a.tilde) {
         if (a.mixed) EH_FD(true, 2, 1, 1, 0, true);
         else EH_FD(true, 2, 1, 1, 0, false);
@@ -267,7 +271,7 @@ k_fdown(GArgs<T> a, int nrhs) {
 // (vu), a.out = e_l (vo)
 
 template <class T, bool FINE, int KIND, int WX, int WY, int NM, int NU2, int TX, int TY, int NT, bool HALF>
-__device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* lds, int nrhs, int tile_x,
+__device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* lds, int r0, int r1, int tile_x,
                                         int tile_y) {
     static_assert(TX * TY == NT, "one tile point per thread");
     const Dims d = a.d[slot], dc = a.dc[slot];
@@ -315,13 +319,13 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     const int64_t rp = (int64_t)rgy * nx + rgx;
     PointOp<T, FINE, KIND, WX, WY, HALF> rop;
     if (RING_EARLY && ring) rop.load(a, slot, d, rgx, rgy, rp);
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = r0; r < r1; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
         const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
         const cplx<T> fmine = mine ? f[mp] : czero<T>();
         const cplx<T> fring = ring ? f[rp] : czero<T>();
-        if (r > 0) __syncthreads();
+        if (r > r0) __syncthreads();
         // u~ = w D^-1 f + P e over region A
         auto stage = [&](int it) {
             const int q = threadIdx.x + it * NT;
@@ -388,16 +392,16 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
 
 template <class T, bool FINE, int NU2, int CFG>
 __global__ void __launch_bounds__(kFUp[CFG].threads)
-k_fup(GArgs<T> a, int nrhs) {
+k_fup(GArgs<T> a, int nrhs, int rch) {
     constexpr int TX = kFUp[CFG].x, TY = kFUp[CFG].y, NT = kFUp[CFG].threads;
     __shared__ cplx<T> lds[fu_lds(TX, TY)];
-    const int slot = blockIdx.z;
-    if (slot >= a.ns) return;
+    const int slot = blockIdx.z % a.ns;
+    const int r0 = (blockIdx.z / a.ns) * rch, r1 = min(nrhs, r0 + rch);
     const int kind = a.kind[slot];
     int tx, ty;
     xcd_tile(tx, ty);
 #define EH_FU(FI, KI, WX, WY, NM, HF) \
-    up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT, HF>(a, slot, lds, nrhs, tx, ty)
+    up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT, HF>(a, slot, lds, r0, r1, tx, ty)
     if (FINE) {
         if (kind == 2 && a.tilde) EH_FU(true, 2, 1, 1, 0, false);
         else if (kind == 2) EH_FU(true, 1, 1, 1, 0, false);

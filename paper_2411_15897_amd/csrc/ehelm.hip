@@ -730,6 +730,23 @@ inline bool fused_cycle(const eh_ctx* c, bool guess) {
 // One level of a V(1, nu2) cycle from a zero guess with the fused legs:
 // f_{l+1} = R (f - X w D^-1 f), the cycle on level l+1, then
 // out = S^nu2 (w D^-1 f + P e_{l+1}).
+// Right-hand sides per workgroup of a fused leg with `tiles` workgroups per
+// slot: the whole batch while the tiles alone give kSplitWgs workgroups or
+// more (the operator in registers then serves every right-hand side);
+// below that the batch is split into chunks, up to one right-hand side per
+// workgroup, so that a small level runs its right-hand sides side by side
+// instead of one after the other.
+#ifndef EH_SPLIT_WGS
+#define EH_SPLIT_WGS 4096
+#endif
+constexpr int kSplitWgs = EH_SPLIT_WGS;
+inline int rhs_chunk(int tiles, int ns, int nrhs) {
+    const int64_t wgs = (int64_t)tiles * ns;
+    if (nrhs <= 1 || wgs >= kSplitWgs) return std::max(nrhs, 1);
+    const int nch = (int)std::min<int64_t>(nrhs, (kSplitWgs + wgs - 1) / wgs);
+    return (nrhs + nch - 1) / nch;
+}
+
 // Fused down leg on level l with tile configuration cfg: a.d / a.dc = levels
 // l / l+1, a.f = f_l, a.out = f_{l+1}.
 template <class T>
@@ -740,10 +757,12 @@ void launch_fdown(eh_ctx* c, const GArgs<T>& a, int l, int cfg, int nrhs) {
         gx = std::max(gx, (a.dc[s].g[0] + k.x - 1) / k.x);
         gy = std::max(gy, (a.dc[s].g[1] + k.y - 1) / k.y);
     }
-    const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)a.ns), blk((unsigned)k.threads);
-#define EH_LFD(CF)                                                                          \
-    if (l == 0) hipLaunchKernelGGL((k_fdown<T, true, CF>), g, blk, 0, c->s, a, nrhs);       \
-    else hipLaunchKernelGGL((k_fdown<T, false, CF>), g, blk, 0, c->s, a, nrhs);
+    const int rch = rhs_chunk(gx * gy, a.ns, nrhs);
+    const int nch = (std::max(nrhs, 1) + rch - 1) / rch;
+    const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)(a.ns * nch)), blk((unsigned)k.threads);
+#define EH_LFD(CF)                                                                               \
+    if (l == 0) hipLaunchKernelGGL((k_fdown<T, true, CF>), g, blk, 0, c->s, a, nrhs, rch);       \
+    else hipLaunchKernelGGL((k_fdown<T, false, CF>), g, blk, 0, c->s, a, nrhs, rch);
     switch (cfg) {
         case 0: EH_LFD(0) break;
         case 1: EH_LFD(1) break;
@@ -763,15 +782,17 @@ void launch_fup(eh_ctx* c, const GArgs<T>& a, int l, int cfg, int nrhs) {
         gx = std::max(gx, (a.d[s].g[0] + k.x - 1) / k.x);
         gy = std::max(gy, (a.d[s].g[1] + k.y - 1) / k.y);
     }
-    const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)a.ns), blk((unsigned)k.threads);
+    const int rch = rhs_chunk(gx * gy, a.ns, nrhs);
+    const int nch = (std::max(nrhs, 1) + rch - 1) / rch;
+    const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)(a.ns * nch)), blk((unsigned)k.threads);
     const bool two = c->o.nu_post == 2;
 #define EH_LFU(CF)                                                                                    \
     if (l == 0) {                                                                                     \
-        if (two) hipLaunchKernelGGL((k_fup<T, true, 2, CF>), g, blk, 0, c->s, a, nrhs);               \
-        else hipLaunchKernelGGL((k_fup<T, true, 1, CF>), g, blk, 0, c->s, a, nrhs);                   \
+        if (two) hipLaunchKernelGGL((k_fup<T, true, 2, CF>), g, blk, 0, c->s, a, nrhs, rch);          \
+        else hipLaunchKernelGGL((k_fup<T, true, 1, CF>), g, blk, 0, c->s, a, nrhs, rch);              \
     } else {                                                                                          \
-        if (two) hipLaunchKernelGGL((k_fup<T, false, 2, CF>), g, blk, 0, c->s, a, nrhs);              \
-        else hipLaunchKernelGGL((k_fup<T, false, 1, CF>), g, blk, 0, c->s, a, nrhs);                  \
+        if (two) hipLaunchKernelGGL((k_fup<T, false, 2, CF>), g, blk, 0, c->s, a, nrhs, rch);         \
+        else hipLaunchKernelGGL((k_fup<T, false, 1, CF>), g, blk, 0, c->s, a, nrhs, rch);             \
     }
     switch (cfg) {
         case 0: EH_LFU(0) break;
