@@ -48,10 +48,16 @@ struct GArgs {
     int tilde;               // H_p built from A~_p (fine couplings of KIND 2)
 };
 
-#define EH_GROUP_POINT(a, DD)                                                   \
-    const int slot = blockIdx.z / (a).maxg2;                                    \
-    const int k = blockIdx.z - slot * (a).maxg2;                                \
-    if (slot >= (a).ns) return;                                                 \
+// Grid: (x, y, maxg2 * ns * chunks).  Workgroup z covers plane k = z %
+// maxg2 of slot (z / maxg2) % ns and right-hand sides [rlo, rhi), chunk
+// z / (maxg2 * ns) of RCH each (RCH = nrhs: the whole batch).  Splitting a
+// batch over workgroups changes only which workgroup computes a right-hand
+// side, not its arithmetic.
+#define EH_GROUP_POINT(a, DD, RCH)                                              \
+    const int zq = blockIdx.z / (a).maxg2;                                      \
+    const int k = blockIdx.z - zq * (a).maxg2;                                  \
+    const int slot = zq % (a).ns;                                               \
+    const int rlo = (zq / (a).ns) * (RCH), rhi = min(nrhs, rlo + (RCH));        \
     const Dims d = (a).DD[slot];                                                \
     if (k >= d.g[2]) return;                                                    \
     const int i = blockIdx.x * blockDim.x + threadIdx.x;                        \
@@ -65,8 +71,8 @@ struct GArgs {
 
 template <class T, int KIND, int DIM, int MODE>
 __global__ void __launch_bounds__(256)
-k_gfine(GArgs<T> a, int nrhs) {
-    EH_GROUP_POINT(a, d)
+k_gfine(GArgs<T> a, int nrhs, int rch) {
+    EH_GROUP_POINT(a, d, rch)
     const T* __restrict__ w0 = a.w[slot][0];
     const T* __restrict__ w1 = a.w[slot][1];
     const T* __restrict__ w2 = a.w[slot][2];
@@ -78,7 +84,7 @@ k_gfine(GArgs<T> a, int nrhs) {
     const T damp = a.damp;
     const cplx<T> sc = cdiv(mk<T>(damp, T(0)), Dp);
     if (MODE == 0) {
-        for (int r = 0; r < nrhs; ++r) out[r * vo + p] = sc * f[r * vf + p];
+        for (int r = rlo; r < rhi; ++r) out[r * vo + p] = sc * f[r * vf + p];
         return;
     }
     FineCoef<T, KIND, DIM> c;
@@ -107,7 +113,7 @@ k_gfine(GArgs<T> a, int nrhs) {
     }
     if (MODE == 4 || MODE == 5) {
 #pragma unroll 2
-        for (int r = 0; r < nrhs; ++r) {
+        for (int r = rlo; r < rhi; ++r) {
             const cplx<T>* __restrict__ fr = f + r * vf;
             const cplx<T> fp = fr[p];
             const cplx<T> u0 = sc * fp;
@@ -127,7 +133,7 @@ k_gfine(GArgs<T> a, int nrhs) {
     const cplx<T>* __restrict__ u = a.u[slot];
     const int64_t vu = a.vu[slot];
 #pragma unroll 2
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = rlo; r < rhi; ++r) {
         const cplx<T>* __restrict__ ur = u + r * vu;
         const cplx<T> up = ur[p];
         cplx<T> offs = czero<T>();
@@ -171,7 +177,7 @@ __global__ void k_dinv(int64_t np, const cplx<T>* __restrict__ coef, T damp, cpl
 
 template <class T, int WX, int WY, int WZ, int MODE, bool HALF>
 __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const Dims& d, int i, int j, int k,
-                                             int64_t p, int64_t sy, int64_t sz, int nrhs) {
+                                             int64_t p, int64_t sy, int64_t sz, int rlo, int rhi) {
     const int64_t np = d.np();
     constexpr int NX = 2 * WX + 1, NY = 2 * WY + 1, NZ = 2 * WZ + 1;
     constexpr int NST = NX * NY * NZ;
@@ -182,7 +188,7 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
     const int64_t vf = a.vf[slot], vo = a.vo[slot];
     const cplx<T> sc = dinv[p];
     if (MODE == 0) {
-        for (int r = 0; r < nrhs; ++r) out[r * vo + p] = sc * f[r * vf + p];
+        for (int r = rlo; r < rhi; ++r) out[r * vo + p] = sc * f[r * vf + p];
         return;
     }
     const cplx<T>* __restrict__ u = a.u[slot];
@@ -211,7 +217,7 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
                     }
                 }
 #pragma unroll 1
-        for (int r = 0; r < nrhs; ++r) {
+        for (int r = rlo; r < rhi; ++r) {
             const cplx<T>* __restrict__ src = (MODE == 4 || MODE == 5) ? f + r * vf : u + r * vu;
             cplx<T> xu = czero<T>();
 #pragma unroll
@@ -237,7 +243,7 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
         }
         return;
     }
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = rlo; r < rhi; ++r) {
         const cplx<T>* __restrict__ ur = u + r * vu;
         const cplx<T>* __restrict__ fr = f + r * vf;
         cplx<T> xu = czero<T>();
@@ -278,24 +284,24 @@ __device__ __forceinline__ void stencil_body(const GArgs<T>& a, int slot, const 
 // kernels are not sized for the wide full-weighting stencils of 3D.
 template <class T, int DIM, int MODE, bool MIXED>
 __global__ void __launch_bounds__(256)
-k_gstencil(GArgs<T> a, int nrhs) {
-    EH_GROUP_POINT(a, d)
+k_gstencil(GArgs<T> a, int nrhs, int rch) {
+    EH_GROUP_POINT(a, d, rch)
     const int kind = a.kind[slot];
     // with full weighting, kinds below DIM are the symmetric, half-stored
     // shear blocks (the mixed restriction is not P^T / 2^d: stored in full)
     if (MIXED) {
-        stencil_body<T, 1, 1, (DIM == 3 ? 1 : 0), MODE, false>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        stencil_body<T, 1, 1, (DIM == 3 ? 1 : 0), MODE, false>(a, slot, d, i, j, k, p, sy, sz, rlo, rhi);
         return;
     }
     if (DIM == 2) {
-        if (kind == 0) stencil_body<T, 1, 2, 0, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else if (kind == 1) stencil_body<T, 2, 1, 0, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else stencil_body<T, 2, 2, 0, MODE, false>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        if (kind == 0) stencil_body<T, 1, 2, 0, MODE, true>(a, slot, d, i, j, k, p, sy, sz, rlo, rhi);
+        else if (kind == 1) stencil_body<T, 2, 1, 0, MODE, true>(a, slot, d, i, j, k, p, sy, sz, rlo, rhi);
+        else stencil_body<T, 2, 2, 0, MODE, false>(a, slot, d, i, j, k, p, sy, sz, rlo, rhi);
     } else {
-        if (kind == 0) stencil_body<T, 1, 2, 2, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else if (kind == 1) stencil_body<T, 2, 1, 2, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else if (kind == 2) stencil_body<T, 2, 2, 1, MODE, true>(a, slot, d, i, j, k, p, sy, sz, nrhs);
-        else stencil_body<T, 2, 2, 2, MODE, false>(a, slot, d, i, j, k, p, sy, sz, nrhs);
+        if (kind == 0) stencil_body<T, 1, 2, 2, MODE, true>(a, slot, d, i, j, k, p, sy, sz, rlo, rhi);
+        else if (kind == 1) stencil_body<T, 2, 1, 2, MODE, true>(a, slot, d, i, j, k, p, sy, sz, rlo, rhi);
+        else if (kind == 2) stencil_body<T, 2, 2, 1, MODE, true>(a, slot, d, i, j, k, p, sy, sz, rlo, rhi);
+        else stencil_body<T, 2, 2, 2, MODE, false>(a, slot, d, i, j, k, p, sy, sz, rlo, rhi);
     }
 }
 
@@ -306,7 +312,7 @@ k_gstencil(GArgs<T> a, int nrhs) {
 
 template <class T, int DIM, int NM, bool MIXED>
 __device__ __forceinline__ void restrict_body(const GArgs<T>& a, int slot, const Dims& dc, int i, int j, int k,
-                                              int64_t p, int nrhs) {
+                                              int64_t p, int rlo, int rhi) {
     using RX = R1<(NM & 1) != 0, MIXED>;
     using RY = R1<(NM & 2) != 0, MIXED>;
     using RZ = R1<(NM & 4) != 0, MIXED>;
@@ -317,7 +323,7 @@ __device__ __forceinline__ void restrict_body(const GArgs<T>& a, int slot, const
     const cplx<T>* r = a.f[slot];
     cplx<T>* fc = a.out[slot];
     const int64_t vsf = a.vf[slot], vsc = a.vo[slot];
-    for (int rr = 0; rr < nrhs; ++rr) {
+    for (int rr = rlo; rr < rhi; ++rr) {
         const cplx<T>* rf = r + rr * vsf;
         cplx<T> s = czero<T>();
 #pragma unroll
@@ -345,7 +351,7 @@ __device__ __forceinline__ void restrict_body(const GArgs<T>& a, int slot, const
 
 template <class T, int DIM, int NM>
 __device__ __forceinline__ void prolong_body(const GArgs<T>& a, int slot, const Dims& df, int i, int j, int k,
-                                             int64_t p, int nrhs) {
+                                             int64_t p, int rlo, int rhi) {
     const Dims dc = a.dc[slot];
     int xi[2], yi[2], zi[2];
     float xw[2], yw[2], zw[2];
@@ -357,7 +363,7 @@ __device__ __forceinline__ void prolong_body(const GArgs<T>& a, int slot, const 
     const cplx<T>* ec = a.f[slot];
     cplx<T>* u = a.out[slot];
     const int64_t vsc = a.vf[slot], vsf = a.vo[slot];
-    for (int rr = 0; rr < nrhs; ++rr) {
+    for (int rr = rlo; rr < rhi; ++rr) {
         const cplx<T>* e = ec + rr * vsc;
         cplx<T> s = czero<T>();
 #pragma unroll
@@ -375,14 +381,14 @@ __device__ __forceinline__ void prolong_body(const GArgs<T>& a, int slot, const 
 
 template <class T, int DIM, bool RESTRICT>
 __global__ void __launch_bounds__(256)
-k_gtransfer(GArgs<T> a, int nrhs) {
-    EH_GROUP_POINT(a, d)
+k_gtransfer(GArgs<T> a, int nrhs, int rch) {
+    EH_GROUP_POINT(a, d, rch)
     const int kind = a.kind[slot];
 #define EH_TB(NM)                                                                       \
     if (RESTRICT) {                                                                     \
-        if (a.mixed) restrict_body<T, DIM, NM, true>(a, slot, d, i, j, k, p, nrhs);     \
-        else restrict_body<T, DIM, NM, false>(a, slot, d, i, j, k, p, nrhs);            \
-    } else prolong_body<T, DIM, NM>(a, slot, d, i, j, k, p, nrhs);
+        if (a.mixed) restrict_body<T, DIM, NM, true>(a, slot, d, i, j, k, p, rlo, rhi);     \
+        else restrict_body<T, DIM, NM, false>(a, slot, d, i, j, k, p, rlo, rhi);            \
+    } else prolong_body<T, DIM, NM>(a, slot, d, i, j, k, p, rlo, rhi);
     if (kind == DIM) { EH_TB(0) }
     else if (kind == 0) { EH_TB(1) }
     else if (kind == 1) { EH_TB(2) }
@@ -481,7 +487,7 @@ struct CoupleArgs {
 template <class T>
 __global__ void __launch_bounds__(256)
 k_gcouple(CoupleArgs a, Dims dc, const cplx<T>* __restrict__ ep, int nrhs, int64_t vr, int64_t ve) {
-    EH_GROUP_POINT(a, d)
+    EH_GROUP_POINT(a, d, nrhs)
     const int kaxis = a.kind[slot];
     int c[3] = {i, j, k};
     const int ck = c[kaxis];
@@ -495,7 +501,7 @@ k_gcouple(CoupleArgs a, Dims dc, const cplx<T>* __restrict__ ep, int nrhs, int64
     cplx<T>* g = (cplx<T>*)a.g[slot];
     const double ihk = a.ih[slot];
     const int64_t vg = a.vg[slot];
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = rlo; r < rhi; ++r) {
         c128 gr = mk(0.0, 0.0);
         if (chi >= 0) gr = gr + ccast<double>(ep[r * ve + chi]);
         if (clo >= 0) gr = gr - ccast<double>(ep[r * ve + clo]);

@@ -625,14 +625,51 @@ GArgs<T> gbase(eh_ctx* c, const int* kinds, int ns, int l, bool coarse_dims_for_
     return a;
 }
 
+// Right-hand sides per workgroup of a multigrid launch (fused leg or
+// per-sweep kernel) with `tiles` workgroups per slot: the whole batch while the tiles alone give kSplitWgs workgroups or
+// more (the operator in registers then serves every right-hand side);
+// below that the batch is split into chunks, up to one right-hand side per
+// workgroup, so that a small level runs its right-hand sides side by side
+// instead of one after the other.
+#ifndef EH_SPLIT_WGS
+#define EH_SPLIT_WGS 4096
+#endif
+constexpr int kSplitWgs = EH_SPLIT_WGS;
+inline int rhs_chunk(int tiles, int ns, int nrhs) {
+    const int64_t wgs = (int64_t)tiles * ns;
+    if (nrhs <= 1 || wgs >= kSplitWgs) return std::max(nrhs, 1);
+    const int nch = (int)std::min<int64_t>(nrhs, (kSplitWgs + wgs - 1) / wgs);
+    return (nrhs + nch - 1) / nch;
+}
+
+// Grid of a per-sweep kernel over the slots of a and the chunks of the
+// batch; rch receives the right-hand sides per workgroup.
 template <class T>
-dim3 ggrid(const GArgs<T>& a, const dim3& blk) {
+dim3 ggrid(const GArgs<T>& a, const dim3& blk, int nrhs, int& rch) {
     int gx = 1, gy = 1;
     for (int s = 0; s < a.ns; ++s) {
         gx = std::max(gx, (int)((a.d[s].g[0] + blk.x - 1) / blk.x));
         gy = std::max(gy, (int)((a.d[s].g[1] + blk.y - 1) / blk.y));
     }
-    return dim3((unsigned)gx, (unsigned)gy, (unsigned)(a.maxg2 * a.ns));
+    rch = rhs_chunk(gx * gy * a.maxg2, a.ns, nrhs);
+    const int nch = (std::max(nrhs, 1) + rch - 1) / rch;
+    return dim3((unsigned)gx, (unsigned)gy, (unsigned)(a.maxg2 * a.ns * nch));
+}
+
+// Restriction (grid = coarse level) or prolongation with correction (grid
+// = fine level) for the slots of t.
+template <class T>
+void launch_transfer(eh_ctx* c, const GArgs<T>& t, const dim3& blk, bool restrict_to_coarse, int nrhs) {
+    int rch = 1;
+    const dim3 g = ggrid(t, blk, nrhs, rch);
+    if (restrict_to_coarse) {
+        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, true>), g, blk, 0, c->s, t, nrhs, rch);
+        else hipLaunchKernelGGL((k_gtransfer<T, 3, true>), g, blk, 0, c->s, t, nrhs, rch);
+    } else {
+        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, false>), g, blk, 0, c->s, t, nrhs, rch);
+        else hipLaunchKernelGGL((k_gtransfer<T, 3, false>), g, blk, 0, c->s, t, nrhs, rch);
+    }
+    HIPCHK(hipGetLastError());
 }
 
 // real couplings stored per fine-level point: d edge weights (A_k), one
@@ -668,9 +705,10 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
                                                                   : (mode == 1 ? KC_FINE_SWEEP : KC_FINE_RESID));
     Timed tm(c, cls, by);
     const dim3 blk = shape_block(c, group_of(c, kind0), l, 0);
-    const dim3 g = ggrid(a, blk);
+    int rch = 1;
+    const dim3 g = ggrid(a, blk, nrhs, rch);
     if (l == 0) {
-#define EH_GF(KIND, DIM, MODE) hipLaunchKernelGGL((k_gfine<T, KIND, DIM, MODE>), g, blk, 0, c->s, a, nrhs)
+#define EH_GF(KIND, DIM, MODE) hipLaunchKernelGGL((k_gfine<T, KIND, DIM, MODE>), g, blk, 0, c->s, a, nrhs, rch)
 #define EH_GF_M(KIND, DIM)                      \
     switch (mode) {                             \
         case 0: EH_GF(KIND, DIM, 0); break;     \
@@ -689,8 +727,8 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
 #undef EH_GF
     } else {
 #define EH_GS(DIM, MODE)                                                                   \
-    if (a.mixed) hipLaunchKernelGGL((k_gstencil<T, DIM, MODE, true>), g, blk, 0, c->s, a, nrhs);  \
-    else hipLaunchKernelGGL((k_gstencil<T, DIM, MODE, false>), g, blk, 0, c->s, a, nrhs)
+    if (a.mixed) hipLaunchKernelGGL((k_gstencil<T, DIM, MODE, true>), g, blk, 0, c->s, a, nrhs, rch);  \
+    else hipLaunchKernelGGL((k_gstencil<T, DIM, MODE, false>), g, blk, 0, c->s, a, nrhs, rch)
 #define EH_GS_M(DIM)                        \
     switch (mode) {                         \
         case 0: EH_GS(DIM, 0); break;       \
@@ -730,22 +768,6 @@ inline bool fused_cycle(const eh_ctx* c, bool guess) {
 // One level of a V(1, nu2) cycle from a zero guess with the fused legs:
 // f_{l+1} = R (f - X w D^-1 f), the cycle on level l+1, then
 // out = S^nu2 (w D^-1 f + P e_{l+1}).
-// Right-hand sides per workgroup of a fused leg with `tiles` workgroups per
-// slot: the whole batch while the tiles alone give kSplitWgs workgroups or
-// more (the operator in registers then serves every right-hand side);
-// below that the batch is split into chunks, up to one right-hand side per
-// workgroup, so that a small level runs its right-hand sides side by side
-// instead of one after the other.
-#ifndef EH_SPLIT_WGS
-#define EH_SPLIT_WGS 4096
-#endif
-constexpr int kSplitWgs = EH_SPLIT_WGS;
-inline int rhs_chunk(int tiles, int ns, int nrhs) {
-    const int64_t wgs = (int64_t)tiles * ns;
-    if (nrhs <= 1 || wgs >= kSplitWgs) return std::max(nrhs, 1);
-    const int nch = (int)std::min<int64_t>(nrhs, (kSplitWgs + wgs - 1) / wgs);
-    return (nrhs + nch - 1) / nch;
-}
 
 // Fused down leg on level l with tile configuration cfg: a.d / a.dc = levels
 // l / l+1, a.f = f_l, a.out = f_{l+1}.
@@ -1001,8 +1023,7 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
         }
         Timed tm(c, KC_RESTRICT, by);
         const dim3 blk = shape_block(c, group_of(c, kinds[0]), l, 1);
-        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, true>), ggrid(t, blk), blk, 0, c->s, t, nrhs);
-        else hipLaunchKernelGGL((k_gtransfer<T, 3, true>), ggrid(t, blk), blk, 0, c->s, t, nrhs);
+        launch_transfer<T>(c, t, blk, true, nrhs);
         HIPCHK(hipGetLastError());
     }
     const int ncalls = (c->o.cycle == 1) ? 2 : 1;
@@ -1020,8 +1041,7 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
         }
         Timed tm(c, KC_PROLONG, by);
         const dim3 blk = shape_block(c, group_of(c, kinds[0]), l, 2);
-        if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, false>), ggrid(t, blk), blk, 0, c->s, t, nrhs);
-        else hipLaunchKernelGGL((k_gtransfer<T, 3, false>), ggrid(t, blk), blk, 0, c->s, t, nrhs);
+        launch_transfer<T>(c, t, blk, false, nrhs);
         HIPCHK(hipGetLastError());
     }
     for (int t = 0; t < nu2; ++t) sweep(1, t == nu2 - 1);
@@ -1237,13 +1257,11 @@ void maybe_autotune(eh_ctx* c, int nrhs) {
                 pt.out[s] = (cplx<T>*)Lv.u; pt.vo[s] = Lv.d.np();
             }
             c->shape[g][l][1] = pick_shape(c, [&](const dim3& blk) {
-                if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, true>), ggrid(rt, blk), blk, 0, c->s, rt, nrhs);
-                else hipLaunchKernelGGL((k_gtransfer<T, 3, true>), ggrid(rt, blk), blk, 0, c->s, rt, nrhs);
+                launch_transfer<T>(c, rt, blk, true, nrhs);
                 HIPCHK(hipGetLastError());
             });
             c->shape[g][l][2] = pick_shape(c, [&](const dim3& blk) {
-                if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, false>), ggrid(pt, blk), blk, 0, c->s, pt, nrhs);
-                else hipLaunchKernelGGL((k_gtransfer<T, 3, false>), ggrid(pt, blk), blk, 0, c->s, pt, nrhs);
+                launch_transfer<T>(c, pt, blk, false, nrhs);
                 HIPCHK(hipGetLastError());
             });
         }
