@@ -197,6 +197,31 @@ def test_batched_equals_single():
     gpu.close()
 
 
+@pytest.mark.parametrize("n,kw", [
+    ((48, 40, 36), dict(levels=3, nu=(2, 2), damping=(0.8, 0.8, 0.2), intergrid="mixed")),
+    ((40, 32), dict(levels=3, cycle="W")),
+    ((96, 80), dict(levels=4)),
+])
+def test_batch_split_over_workgroups_is_bitwise(n, kw):
+    """A batch of 7 is spread over workgroups on levels with few tiles
+    (chunks of one right-hand side on the small levels; 2, 2, 2, 1 in the
+    3D fine-level shear sweeps with the default 64 x 4 blocks): the
+    per-sweep kernels (3D, W-cycles) and the fused legs give every
+    right-hand side bitwise what it gets alone, in complex64 and
+    complex128."""
+    say("batch split", n, kw)
+    r = None
+    for prec in (32, 64):
+        gpu, s = make(n, seed=17, alpha=0.4, mg_precision=prec, **kw)
+        if r is None:
+            r = crand((7, s.ndof), 18)
+        zb = gpu.apply_preconditioner(to_dev(r)).cpu().numpy()
+        for k in range(7):
+            zk = gpu.apply_preconditioner(to_dev(r[k:k + 1])).cpu().numpy()[0]
+            assert np.array_equal(zb[k], zk), (prec, k)
+        gpu.close()
+
+
 def test_gradient_parity():
     """eh_misfit + adjoint solve + eh_gradient against the oracle's
     gradient with direct solves."""
