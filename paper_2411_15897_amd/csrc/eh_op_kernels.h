@@ -28,6 +28,12 @@ __device__ __forceinline__ int64_t face_cell(const Dims& dc, int kaxis, int i, i
     return ((int64_t)c[2] * dc.g[1] + c[1]) * dc.g[0] + c[0];
 }
 
+// Launch: blockDim (64, 4), gridDim (x tiles, y tiles, planes x chunks of
+// the batch); workgroup z takes plane z % planes and right-hand sides
+// [c * rch, min(nrhs, c * rch + rch)) with c = z / planes, so a batch on a
+// small grid is spread over more workgroups (the arithmetic of each
+// right-hand side is unchanged).
+//
 // Residual form (RES), for the FGMRES cycle starts: the launch writes
 // r = b - H x instead of H x and, per right-hand side, one partial sum of
 // |r|^2 per workgroup (a butterfly within each wavefront, then the four
@@ -42,14 +48,16 @@ struct ResArgs {
     int blk0;            // first workgroup index of this launch
 };
 
-__device__ __forceinline__ void res_partial(const ResArgs& ra, int r, double v) {
+__device__ __forceinline__ void res_partial(const ResArgs& ra, int r, int kz, double v) {
     __shared__ double sv[4];
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((tid & 63) == 0) sv[tid >> 6] = v;
     __syncthreads();
     if (tid == 0) {
-        const int blk = ra.blk0 + (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        // the workgroup's place in the plane grid (kz = its plane), not its
+        // chunk of the batch: every chunk writes the rows of its own RHS
+        const int blk = ra.blk0 + (kz * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
         ra.partial[(int64_t)r * ra.nblk + blk] = mk((sv[0] + sv[1]) + (sv[2] + sv[3]), 0.0);
     }
     __syncthreads();       // sv is reused by the next right-hand side
@@ -60,10 +68,11 @@ __global__ void __launch_bounds__(256)
 k_op_face(Dims d, Dims dc, int kaxis, const double* __restrict__ w0, const double* __restrict__ w1,
           const double* __restrict__ w2, const c128* __restrict__ D0, const cplx<Tin>* __restrict__ u,
           const cplx<Tin>* __restrict__ pf, double ihk, c128* __restrict__ y, int nrhs,
-          int64_t vs_in, int64_t vs_out, ResArgs ra) {
+          int64_t vs_in, int64_t vs_out, ResArgs ra, int rch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const int k = blockIdx.z % d.g[2];
+    const int rlo = (blockIdx.z / d.g[2]) * rch, rhi = min(nrhs, rlo + rch);
     const bool in = i < d.g[0] && j < d.g[1];
     if (!RES && !in) return;
     const int64_t sy = d.g[0], sz = (int64_t)d.g[0] * d.g[1];
@@ -77,7 +86,7 @@ k_op_face(Dims d, Dims dc, int kaxis, const double* __restrict__ w0, const doubl
         chi = face_cell(dc, kaxis, i, j, k, 0);
         clo = face_cell(dc, kaxis, i, j, k, -1);
     }
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = rlo; r < rhi; ++r) {
         c128 yv = mk(0.0, 0.0);
         if (in) {
             const cplx<Tin>* ur = u + r * vs_in;
@@ -99,7 +108,7 @@ k_op_face(Dims d, Dims dc, int kaxis, const double* __restrict__ w0, const doubl
             if (RES) yv = ra.b[r * vs_out + p] - yv;
             y[r * vs_out + p] = yv;
         }
-        if (RES) res_partial(ra, r, yv.re * yv.re + yv.im * yv.im);
+        if (RES) res_partial(ra, r, k, yv.re * yv.re + yv.im * yv.im);
     }
 }
 
@@ -108,10 +117,11 @@ __global__ void __launch_bounds__(256)
 k_op_cell(Dims dc, const cplx<Tin>* __restrict__ u0, const cplx<Tin>* __restrict__ u1,
           const cplx<Tin>* __restrict__ u2, const cplx<Tin>* __restrict__ pf,
           const double* __restrict__ C, double ih0, double ih1, double ih2, c128* __restrict__ y,
-          int nrhs, int64_t vs_in, int64_t vs_out, ResArgs ra) {
+          int nrhs, int64_t vs_in, int64_t vs_out, ResArgs ra, int rch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const int k = blockIdx.z % dc.g[2];
+    const int rlo = (blockIdx.z / dc.g[2]) * rch, rhi = min(nrhs, rlo + rch);
     const bool in = i < dc.g[0] && j < dc.g[1];
     if (!RES && !in) return;
     const int64_t p = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
@@ -121,7 +131,7 @@ k_op_cell(Dims dc, const cplx<Tin>* __restrict__ u0, const cplx<Tin>* __restrict
     const int64_t f2 = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
     const int64_t s2 = (int64_t)dc.g[0] * dc.g[1];
     const double Cp = in ? C[p] : 0.0;
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = rlo; r < rhi; ++r) {
         c128 yv = mk(0.0, 0.0);
         if (in) {
             const int64_t o = r * vs_in;
@@ -133,7 +143,7 @@ k_op_cell(Dims dc, const cplx<Tin>* __restrict__ u0, const cplx<Tin>* __restrict
             if (RES) yv = ra.b[r * vs_out + p] - yv;
             y[r * vs_out + p] = yv;
         }
-        if (RES) res_partial(ra, r, yv.re * yv.re + yv.im * yv.im);
+        if (RES) res_partial(ra, r, k, yv.re * yv.re + yv.im * yv.im);
     }
 }
 

@@ -1280,31 +1280,42 @@ void launch_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrh
     const cplx<Tin>* X = (const cplx<Tin>*)x;
     const cplx<Tin>* pf = X + c->off[c->dim];
     const c128* b = ra.b;
+    // a batch on a small grid is spread over chunks of right-hand sides in z
+    auto chunked = [&](const Dims& d, int& rch) {
+        const dim3 g = grid_of(d);
+        rch = rhs_chunk((int)(g.x * g.y * g.z), 1, nrhs);
+        const int nch = (std::max(nrhs, 1) + rch - 1) / rch;
+        return dim3(g.x, g.y, g.z * (unsigned)nch);
+    };
     for (int k = 0; k < c->dim; ++k) {
         const Dims& d = c->dface[k];
         const dim3 g = grid_of(d);
+        int rch = 1;
+        const dim3 gc = chunked(d, rch);
         ra.b = RES ? b + c->off[k] : nullptr;
         if (c->dim == 2)
-            hipLaunchKernelGGL((k_op_face<Tin, 2, RES>), g, kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
+            hipLaunchKernelGGL((k_op_face<Tin, 2, RES>), gc, kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
                                c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
-                               y + c->off[k], nrhs, vx, vy, ra);
+                               y + c->off[k], nrhs, vx, vy, ra, rch);
         else
-            hipLaunchKernelGGL((k_op_face<Tin, 3, RES>), g, kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
+            hipLaunchKernelGGL((k_op_face<Tin, 3, RES>), gc, kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
                                c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
-                               y + c->off[k], nrhs, vx, vy, ra);
+                               y + c->off[k], nrhs, vx, vy, ra, rch);
         HIPCHK(hipGetLastError());
-        ra.blk0 += (int)(g.x * g.y * g.z);
+        ra.blk0 += (int)(g.x * g.y * g.z);      // partial sums per plane-grid workgroup
     }
     const cplx<Tin>* u2 = c->dim == 3 ? X + c->off[2] : X;
     ra.b = RES ? b + c->off[c->dim] : nullptr;
+    int rch = 1;
+    const dim3 gc = chunked(c->dcell, rch);
     if (c->dim == 2)
-        hipLaunchKernelGGL((k_op_cell<Tin, 2, RES>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, X + c->off[0],
+        hipLaunchKernelGGL((k_op_cell<Tin, 2, RES>), gc, kBlock, 0, c->s, c->dcell, X + c->off[0],
                            X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
-                           y + c->off[c->dim], nrhs, vx, vy, ra);
+                           y + c->off[c->dim], nrhs, vx, vy, ra, rch);
     else
-        hipLaunchKernelGGL((k_op_cell<Tin, 3, RES>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell, X + c->off[0],
+        hipLaunchKernelGGL((k_op_cell<Tin, 3, RES>), gc, kBlock, 0, c->s, c->dcell, X + c->off[0],
                            X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
-                           y + c->off[c->dim], nrhs, vx, vy, ra);
+                           y + c->off[c->dim], nrhs, vx, vy, ra, rch);
     HIPCHK(hipGetLastError());
 }
 
