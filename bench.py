@@ -59,9 +59,21 @@ def cpu_baseline(wl, iters_ref, n_iters):
         "cores": 1,
         "kind": "oracle",
         "sample": (f"{res.iters} FGMRES iterations of the oracle (FP64 sparse V-cycles, "
-                   f"setup excluded) on the same 1024^2 workload, {per_it:.3f} s/iteration, "
+                   f"setup excluded) on the same workload ({wl.name}), {per_it:.3f} s/iteration, "
                    f"extrapolated to the GPU FP64 iteration count {iters_ref}"),
+        "host": {"nproc": os.cpu_count(), "cpu": host_cpu_model()},
     }
+
+
+def host_cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 # the multigrid cycles proper (smoothing, residuals, transfers, coarsest
