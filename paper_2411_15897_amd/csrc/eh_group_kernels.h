@@ -486,8 +486,8 @@ struct CoupleArgs {
 
 template <class T>
 __global__ void __launch_bounds__(256)
-k_gcouple(CoupleArgs a, Dims dc, const cplx<T>* __restrict__ ep, int nrhs, int64_t vr, int64_t ve) {
-    EH_GROUP_POINT(a, d, nrhs)
+k_gcouple(CoupleArgs a, Dims dc, const cplx<T>* __restrict__ ep, int nrhs, int64_t vr, int64_t ve, int rch) {
+    EH_GROUP_POINT(a, d, rch)
     const int kaxis = a.kind[slot];
     int c[3] = {i, j, k};
     const int ck = c[kaxis];

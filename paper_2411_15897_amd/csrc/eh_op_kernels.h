@@ -156,8 +156,15 @@ k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
              const c128* __restrict__ r2, const c128* __restrict__ rp,
              const double* __restrict__ mu, const c128* __restrict__ mcell, double om2,
              double ih0, double ih1, double ih2, cplx<T>* __restrict__ t, int nrhs,
-             int64_t vs_in, int64_t vs_out, const double* __restrict__ rs, int64_t rss) {
-    EH_POINT_INDEX(dc)
+             int64_t vs_in, int64_t vs_out, const double* __restrict__ rs, int64_t rss, int rch) {
+    // grid z: planes x chunks of the batch, as for the operator kernels
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z % dc.g[2];
+    const int rlo = (blockIdx.z / dc.g[2]) * rch, rhi = min(nrhs, rlo + rch);
+    if (i >= dc.g[0] || j >= dc.g[1]) return;
+    const int64_t sy = dc.g[0], sz = (int64_t)dc.g[0] * dc.g[1];
+    const int64_t p = k * sz + j * sy + i;
     const int64_t f0 = ((int64_t)k * dc.g[1] + j) * (dc.g[0] + 1) + i;
     const int64_t f1 = ((int64_t)k * (dc.g[1] + 1) + j) * dc.g[0] + i;
     const int64_t f2 = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
@@ -173,7 +180,7 @@ k_distribute(Dims dc, const c128* __restrict__ r0, const c128* __restrict__ r1,
         mnb[a][1] = (ci[a] + 1 < dc.g[a]) ? mu[p + st[a]] : 0.0;
     }
     const c128 mc = mcell[p];
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = rlo; r < rhi; ++r) {
         const int64_t o = r * vs_in;
         c128 div = ih0 * (r0[o + f0 + 1] - r0[o + f0]);
         div = div + ih1 * (r1[o + f1 + dc.g[0]] - r1[o + f1]);

@@ -1370,18 +1370,21 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
     const c128* r2 = d == 3 ? r + c->off[2] : r;
     {
     Timed tm(c, KC_DISTRIBUTE, 24.0 * c->ncell + (double)nrhs * (c->ndof * 16.0 + c->ncell * sizeof(cplx<T>)));
+    const dim3 g0 = grid_of(c->dcell);
+    const int rch = rhs_chunk((int)(g0.x * g0.y * g0.z), 1, nrhs);
+    const dim3 g(g0.x, g0.y, g0.z * (unsigned)((std::max(nrhs, 1) + rch - 1) / rch));
     auto launch = [&](auto tilde_tag) {
         constexpr bool TILDE = decltype(tilde_tag)::value;
         if (d == 2)
-            hipLaunchKernelGGL((k_distribute<T, 2, TILDE>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell,
+            hipLaunchKernelGGL((k_distribute<T, 2, TILDE>), g, kBlock, 0, c->s, c->dcell,
                                r + c->off[0], r + c->off[1], r2, r + c->off[d], c->mu, c->mcell,
                                c->omega * c->omega, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f,
-                               nrhs, vr, c->ncell, rs, rss);
+                               nrhs, vr, c->ncell, rs, rss, rch);
         else
-            hipLaunchKernelGGL((k_distribute<T, 3, TILDE>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell,
+            hipLaunchKernelGGL((k_distribute<T, 3, TILDE>), g, kBlock, 0, c->s, c->dcell,
                                r + c->off[0], r + c->off[1], r2, r + c->off[d], c->mu, c->mcell,
                                c->omega * c->omega, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], (cplx<T>*)Lp.f,
-                               nrhs, vr, c->ncell, rs, rss);
+                               nrhs, vr, c->ncell, rs, rss, rch);
     };
     if (c->o.ap_variant == 1) launch(std::true_type{});
     else launch(std::false_type{});
@@ -1430,8 +1433,10 @@ void apply_M(eh_ctx* c, const c128* r, int64_t vr, void* z, int64_t vz, int nrhs
             gx = std::max(gx, (ca.d[k].g[0] + 63) / 64);
             gy = std::max(gy, (ca.d[k].g[1] + 3) / 4);
         }
-        hipLaunchKernelGGL((k_gcouple<T>), dim3(gx, gy, ca.maxg2 * d), kBlock, 0, c->s, ca, c->dcell,
-                           (const cplx<T>*)ep, nrhs, vr, vz);
+        const int rch = rhs_chunk(gx * gy * ca.maxg2, d, nrhs);
+        const int nch = (std::max(nrhs, 1) + rch - 1) / rch;
+        hipLaunchKernelGGL((k_gcouple<T>), dim3(gx, gy, ca.maxg2 * d * nch), kBlock, 0, c->s, ca, c->dcell,
+                           (const cplx<T>*)ep, nrhs, vr, vz, rch);
         HIPCHK(hipGetLastError());
     }
     gcycle<T>(c, kinds, d, 0, f, vf, out, vo, false, nrhs);
@@ -1783,12 +1788,12 @@ eh_status apply_Z_impl(eh_ctx* c, const c128* v, c128* y, double tol, int maxit)
             hipLaunchKernelGGL((k_distribute<double, 2, TILDE>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell,
                                z2 + c->off[0], z2 + c->off[1], r2, z2 + c->off[d], c->mu, c->mcell,
                                c->omega * c->omega, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], y, 1, c->ndof,
-                               c->ncell, (const double*)nullptr, (int64_t)0);
+                               c->ncell, (const double*)nullptr, (int64_t)0, 1);
         else
             hipLaunchKernelGGL((k_distribute<double, 3, TILDE>), grid_of(c->dcell), kBlock, 0, c->s, c->dcell,
                                z2 + c->off[0], z2 + c->off[1], r2, z2 + c->off[d], c->mu, c->mcell,
                                c->omega * c->omega, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2], y, 1, c->ndof,
-                               c->ncell, (const double*)nullptr, (int64_t)0);
+                               c->ncell, (const double*)nullptr, (int64_t)0, 1);
     };
     if (c->o.ap_variant == 1) launch(std::true_type{});
     else launch(std::false_type{});
