@@ -86,6 +86,16 @@ typedef struct {
     int ap_variant;         /* 0: A_p = B B^T diag(mu) - w^2 M_p (eq. Ap) in the distributor and in
                                H_p = B B^T + A_p C (eq. Hp), the paper's choice; 1: the alternative of the
                                Remark after eq. prec, A~_p = B A_f(mu) B^T - w^2 M_p, in both */
+    int coarse_solver;      /* direct solve of the coarsest level (Section 4.4.1), FP64 either way:
+                               1: explicit dense inverse (Gauss-Jordan, partial pivoting), applied as a
+                                  matrix-vector product; at most 6000 points per block;
+                               2: block-tridiagonal LU over groups of planes (lines in 2D) normal to one
+                                  axis, each group as wide as the coarse stencil's half width along it;
+                                  Schur complements inverted by blocked Gauss-Jordan (partial pivoting
+                                  inside 32 x 32 pivot blocks), applied as a forward and a back sweep of
+                                  one launch per group; the factors are checked at create by one solve
+                                  whose FP64 residual must stay below 1e-8 (EH_ERR_ARG otherwise);
+                               0: 1 while every block's coarsest grid has at most 6000 points, else 2 */
 } eh_opts;
 
 typedef struct {
@@ -97,8 +107,8 @@ typedef struct {
 
 /* Fill `opts` with defaults: 3 levels, V(1,2), damping 0.8/0.8/0.3,
  * alpha 0.1, complex64 multigrid, restart 20, 20-cell layer on all sides but
- * the top, gamma0 = 0.01 pi, full-weighting intergrid (Sections 4 and
- * 4.4.1). */
+ * the top, gamma0 = 0.01 pi, full-weighting intergrid, automatic choice of
+ * the coarsest solver (Sections 4 and 4.4.1). */
 void eh_default_opts(eh_opts *opts);
 
 /* Set up the operator and the preconditioner for one grid, medium and

@@ -25,6 +25,7 @@
 #include "eh_grad_kernels.h"
 #include "eh_group_kernels.h"
 #include "eh_fused_kernels.h"
+#include "eh_coarse_kernels.h"
 
 using namespace eh;
 
@@ -68,6 +69,18 @@ struct Level {
     int nstored() const { return half ? (w.nst() + 1) / 2 : w.nst(); }
 };
 
+// Block-tridiagonal factors of a coarsest level (eh_coarse_kernels.h).
+struct BTData {
+    BTPart pt{};
+    std::vector<int64_t> goff;   // first entry of each group in the group order (nb + 1)
+    std::vector<int64_t> offF;   // F_I = [S_I^-1 | -S_I^-1 L_I] in mats
+    std::vector<int64_t> offB;   // B_I = -S_I^-1 U_I in mats
+    c128* mats = nullptr;
+    int* perm = nullptr;         // group order -> point index (N)
+    c128* y = nullptr;           // FP64 work vector, nrhs_cap * N
+    double bytes = 0.0;          // matrix bytes read by one solve
+};
+
 struct Block {
     int kind = 0;            // 0..dim-1: A_{kind+1}; dim: H_p
     int nodal_mask = 0;      // bit a: unknowns nodal along axis a
@@ -75,8 +88,13 @@ struct Block {
     void* fw[3] = {nullptr, nullptr, nullptr};   // fine couplings (multigrid precision)
     void* fD = nullptr;                          // fine diagonal (multigrid precision)
     int64_t Nc = 0;
-    c128* Ainv = nullptr;                        // coarsest inverse, FP64, row-major
+    c128* Ainv = nullptr;                        // coarsest inverse, FP64, row-major (dense solve)
+    bool bt = false;                             // coarsest solved block-tridiagonally
+    BTData btd;
 };
+
+// Largest coarsest grid solved through an explicit dense inverse.
+constexpr int64_t kDenseMax = 6000;
 
 dim3 grid_of(const Dims& d) {
     return dim3((unsigned)((d.g[0] + 63) / 64), (unsigned)((d.g[1] + 3) / 4), (unsigned)d.g[2]);
@@ -185,6 +203,7 @@ struct eh_ctx {
     // (0: down leg, 1: up leg), indices into kFDown / kFUp
     int fcfg[2][kMaxLevels][2] = {};
     int tuned_nrhs = 0;
+    bool use_bt = false;          // coarsest levels solved block-tridiagonally (else dense inverse)
 
     template <class P>
     P* alloc(size_t count) {
@@ -469,6 +488,171 @@ std::vector<c128> fine_stencil(const eh_ctx* c, const Block& B, const std::vecto
     return st;
 }
 
+// Coarsest solve by an explicit dense inverse: Gauss-Jordan with partial
+// pivoting (FP64) on [X | I], applied later as a matrix-vector product.
+void build_dense(eh_ctx* c, Block& B, c128* prev, const Widths& wprev, const Dims& dc) {
+    const int64_t N = dc.np();
+    // the dense inverse costs 16 N^2 bytes and O(N^3) setup: keep N modest
+    if (N > kDenseMax)
+        throw ArgError{"coarsest grid too large for the dense direct solve (use the block-tridiagonal solve)"};
+    c128* M = c->alloc<c128>((size_t)N * 2 * N);
+    hipLaunchKernelGGL(k_dense_from_stencil, dim3(lin_grid(N, 64, 1 << 30)), dim3(64), 0, 0, dc, wprev, prev, M);
+    HIPCHK(hipGetLastError());
+    int64_t* piv = c->alloc<int64_t>(1);
+    c128* pval = c->alloc<c128>(1);
+    c128* mult = c->alloc<c128>(N);
+    const unsigned gcols = lin_grid(2 * N);
+    for (int64_t kk = 0; kk < N; ++kk) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, 0, N, kk, M, piv, pval);
+        hipLaunchKernelGGL(k_gj_swap_scale, dim3(gcols), dim3(256), 0, 0, N, kk, M, piv, pval);
+        hipLaunchKernelGGL(k_gj_column, dim3(lin_grid(N)), dim3(256), 0, 0, N, kk, M, mult);
+        hipLaunchKernelGGL(k_gj_eliminate, dim3(gcols, (unsigned)N), dim3(256), 0, 0, N, kk, M, mult);
+    }
+    HIPCHK(hipGetLastError());
+    B.Nc = N;
+    B.Ainv = c->alloc<c128>((size_t)N * N);
+    hipLaunchKernelGGL(k_gj_extract, dim3(lin_grid(N * N, 256, 1 << 30)), dim3(256), 0, 0, N, M, B.Ainv);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    c->release(M);
+    c->release(piv);
+    c->release(pval);
+    c->release(mult);
+}
+
+
+template <class T>
+void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const int64_t* vf, void* const* out,
+              const int64_t* vo, int nrhs);
+
+// Coarsest solve by block-tridiagonal LU over groups of planes normal to the
+// axis that gives the smallest groups (eh_coarse_kernels.h): every group's
+// Schur complement is inverted by blocked Gauss-Jordan; the factors are
+// checked by solving one system and recomputing its residual in FP64.
+void build_bt(eh_ctx* c, Block& B, c128* st, const Widths& w, const Dims& d) {
+    BTData& T = B.btd;
+    BTPart& pt = T.pt;
+    pt.d = d;
+    pt.w = w;
+    const int64_t N = d.np();
+    int best = -1;
+    double bestb = 0.0;
+    for (int a = 0; a < c->dim; ++a) {
+        if (w.w[a] < 1) continue;
+        const double bs = (double)w.w[a] * (double)N / d.g[a];
+        if (best < 0 || bs < bestb) { best = a; bestb = bs; }
+    }
+    if (best < 0) throw ArgError{"internal: no axis for the block-tridiagonal coarsest solve"};
+    pt.ax = best;
+    pt.a1 = best == 0 ? 1 : 0;
+    pt.a2 = best == 2 ? 1 : 2;
+    pt.gsz = w.w[best];
+    pt.nb = (d.g[best] + pt.gsz - 1) / pt.gsz;
+    pt.P = (int)(N / d.g[best]);
+    const int nb = pt.nb;
+    T.goff.assign(nb + 1, 0);
+    T.offF.assign(nb, 0);
+    T.offB.assign(nb, 0);
+    int64_t tot = 0;
+    int bmax = 0;
+    for (int I = 0; I < nb; ++I) {
+        const int64_t b = pt.bsize(I);
+        T.goff[I + 1] = T.goff[I] + b;
+        T.offF[I] = tot;
+        tot += b * (b + pt.bsize(I - 1));
+        bmax = std::max(bmax, (int)b);
+    }
+    for (int I = 0; I < nb; ++I) {
+        T.offB[I] = tot;
+        tot += (int64_t)pt.bsize(I) * pt.bsize(I + 1);
+    }
+    T.bytes = (double)tot * sizeof(c128);
+    T.mats = c->alloc<c128>((size_t)tot);
+    {
+        std::vector<int> perm((size_t)N);
+        for (int I = 0; I < nb; ++I)
+            for (int m = 0; m < pt.bsize(I); ++m) {
+                int cc[3];
+                pt.coords(I, m, cc);
+                perm[(size_t)(T.goff[I] + m)] = (int)pt.point(cc);
+            }
+        T.perm = c->alloc<int>((size_t)N);
+        HIPCHK(hipMemcpy(T.perm, perm.data(), (size_t)N * sizeof(int), hipMemcpyHostToDevice));
+    }
+    const int bpmax = (bmax + GJB - 1) / GJB * GJB;
+    c128* M = c->alloc<c128>((size_t)bpmax * bpmax);
+    int* bad = c->alloc<int>(1);
+    HIPCHK(hipMemset(bad, 0, sizeof(int)));
+    for (int I = 0; I < nb; ++I) {
+        const int b = pt.bsize(I), bprev = pt.bsize(I - 1), bnext = pt.bsize(I + 1);
+        const int bp = (b + GJB - 1) / GJB * GJB;
+        hipLaunchKernelGGL(k_bt_schur, dim3((unsigned)((bp + 255) / 256), (unsigned)bp), dim3(256), 0, 0, pt, st, I,
+                           I > 0 ? T.mats + T.offB[I - 1] : nullptr, M, bp);
+        const unsigned t64 = (unsigned)((bp + 63) / 64);
+        for (int K = 0; K < bp / GJB; ++K) {
+            hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, 0, M, bp, K, bad);
+            hipLaunchKernelGGL(k_gj_rowpanel, dim3(t64), dim3(256), 0, 0, M, bp, K);
+            hipLaunchKernelGGL(k_gj_update, dim3(t64, t64), dim3(256), 0, 0, M, bp, K);
+            hipLaunchKernelGGL(k_gj_colpanel, dim3(t64), dim3(256), 0, 0, M, bp, K);
+        }
+        const int ldF = b + bprev;
+        hipLaunchKernelGGL(k_bt_store_inv, dim3((unsigned)((b + 255) / 256), (unsigned)b), dim3(256), 0, 0, M, bp, b,
+                           T.mats + T.offF[I], ldF);
+        if (I > 0)
+            hipLaunchKernelGGL(k_bt_couple, dim3((unsigned)((bprev + 255) / 256), (unsigned)b), dim3(256), 0, 0, pt,
+                               st, I, -1, M, bp, T.mats + T.offF[I] + b, ldF);
+        if (I < nb - 1)
+            hipLaunchKernelGGL(k_bt_couple, dim3((unsigned)((bnext + 255) / 256), (unsigned)b), dim3(256), 0, 0, pt,
+                               st, I, +1, M, bp, T.mats + T.offB[I], bnext);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipDeviceSynchronize());
+    int hbad = 0;
+    HIPCHK(hipMemcpy(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost));
+    c->release(M);
+    c->release(bad);
+    if (hbad) throw ArgError{"coarsest level: zero pivot in the block-tridiagonal factorisation"};
+    B.bt = true;
+    B.Nc = N;
+    // accuracy check: solve X x = f for a fixed f, recompute f - X x in FP64
+    std::vector<c128> hf((size_t)N), hr((size_t)N);
+    for (int64_t q = 0; q < N; ++q) hf[(size_t)q] = mk(std::sin(0.37 * (double)q + 0.1), std::cos(0.91 * (double)q));
+    c128* df = c->alloc<c128>((size_t)N);
+    c128* dx = c->alloc<c128>((size_t)N);
+    c128* dy = c->alloc<c128>((size_t)N);
+    T.y = c->alloc<c128>((size_t)N);
+    HIPCHK(hipMemcpy(df, hf.data(), (size_t)N * sizeof(c128), hipMemcpyHostToDevice));
+    {
+        hipStream_t keep = c->s;
+        c->s = nullptr;
+        const int kinds[1] = {B.kind};
+        const void* fp[1] = {df};
+        void* xp[1] = {dx};
+        const int64_t vv[1] = {N};
+        bt_solve<double>(c, kinds, 1, fp, vv, xp, vv, 1);
+        c->s = keep;
+    }
+    hipLaunchKernelGGL(k_stencil_f64, dim3(lin_grid(N, 256, 1 << 30)), dim3(256), 0, 0, d, w, st, dx, dy);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(hr.data(), dy, (size_t)N * sizeof(c128), hipMemcpyDeviceToHost));
+    double rn = 0.0, fn = 0.0;
+    for (int64_t q = 0; q < N; ++q) {
+        const c128 e = hr[(size_t)q] - hf[(size_t)q];
+        rn += cabs2(e);
+        fn += cabs2(hf[(size_t)q]);
+    }
+    c->release(df);
+    c->release(dx);
+    c->release(dy);
+    const double rel = std::sqrt(rn / fn);
+    if (!(rel < 1e-8)) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "coarsest level: block-tridiagonal factorisation inaccurate (relative "
+                      "residual %.3g)", rel);
+        throw ArgError{msg};
+    }
+}
+
 // Galerkin hierarchy (FP64 on the device) and coarsest inverse.
 void build_hierarchy(eh_ctx* c, Block& B, const std::vector<c128>& st0) {
     const int L = (int)B.lev.size();
@@ -541,34 +725,9 @@ void build_hierarchy(eh_ctx* c, Block& B, const std::vector<c128>& st0) {
     HIPCHK(hipMemcpy(&ov, overflow, sizeof(int), hipMemcpyDeviceToHost));
     c->release(overflow);
     if (ov) throw ArgError{"internal: Galerkin stencil exceeded its width"};
-    // coarsest: dense inverse by Gauss-Jordan with partial pivoting (FP64)
     const Level& Lc = B.lev[L - 1];
-    const int64_t N = Lc.d.np();
-    // the dense inverse costs 16 N^2 bytes and O(N^3) setup: keep N modest
-    if (N > 6000) throw ArgError{"coarsest grid too large for the dense direct solve (use more levels)"};
-    c128* M = c->alloc<c128>((size_t)N * 2 * N);
-    hipLaunchKernelGGL(k_dense_from_stencil, dim3(lin_grid(N, 64, 1 << 30)), dim3(64), 0, 0, Lc.d, wprev, prev, M);
-    HIPCHK(hipGetLastError());
-    int64_t* piv = c->alloc<int64_t>(1);
-    c128* pval = c->alloc<c128>(1);
-    c128* mult = c->alloc<c128>(N);
-    const unsigned gcols = lin_grid(2 * N);
-    for (int64_t kk = 0; kk < N; ++kk) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, 0, N, kk, M, piv, pval);
-        hipLaunchKernelGGL(k_gj_swap_scale, dim3(gcols), dim3(256), 0, 0, N, kk, M, piv, pval);
-        hipLaunchKernelGGL(k_gj_column, dim3(lin_grid(N)), dim3(256), 0, 0, N, kk, M, mult);
-        hipLaunchKernelGGL(k_gj_eliminate, dim3(gcols, (unsigned)N), dim3(256), 0, 0, N, kk, M, mult);
-    }
-    HIPCHK(hipGetLastError());
-    B.Nc = N;
-    B.Ainv = c->alloc<c128>((size_t)N * N);
-    hipLaunchKernelGGL(k_gj_extract, dim3(lin_grid(N * N, 256, 1 << 30)), dim3(256), 0, 0, N, M, B.Ainv);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipDeviceSynchronize());
-    c->release(M);
-    c->release(piv);
-    c->release(pval);
-    c->release(mult);
+    if (c->use_bt) build_bt(c, B, prev, wprev, Lc.d);
+    else build_dense(c, B, prev, wprev, Lc.d);
     c->release(prev);
 }
 
@@ -584,6 +743,12 @@ void ensure_mg_workspace(eh_ctx* c, int nrhs) {
                 *pp = c->alloc<char>((size_t)L.d.np() * nrhs * cs);
             }
         }
+    for (int b = 0; b < c->nblocks; ++b) {
+        BTData& T = c->blk[b].btd;
+        if (!c->blk[b].bt) continue;
+        c->release(T.y);
+        T.y = c->alloc<c128>((size_t)T.pt.d.np() * nrhs);
+    }
     c->nrhs_cap = nrhs;
 }
 
@@ -759,6 +924,71 @@ template <class T>
 void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, const int64_t* vf,
             void* const* out, const int64_t* vo, bool guess, int nrhs);
 
+// Coarsest solve e = X_c^-1 f for the blocks kinds[0..ns) by the block-
+// tridiagonal factors: forward sweep over the groups, then back sweep, one
+// launch per group step for all blocks of the launch (a block with fewer
+// groups idles in the last steps).  Right-hand sides in chunks of up to 8
+// per workgroup, each matrix row read once per chunk.
+template <class T>
+void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const int64_t* vf, void* const* out,
+              const int64_t* vo, int nrhs) {
+    if (ns > BT_MAXS) throw ArgError{"internal: too many blocks for one block-tridiagonal launch"};
+    const int RB = nrhs >= 5 ? 8 : nrhs >= 3 ? 4 : nrhs;
+    const unsigned chunks = (unsigned)((nrhs + RB - 1) / RB);
+    int maxnb = 0;
+    double by = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        const BTData& bd = c->blk[kinds[s]].btd;
+        maxnb = std::max(maxnb, bd.pt.nb);
+        const double N = (double)bd.pt.d.np();
+        by += bd.bytes * chunks + N * nrhs * (2.0 * sizeof(cplx<T>) + 4.0 * sizeof(c128));
+    }
+    Timed tm(c, KC_DENSE, by);
+    auto launch = [&](bool fwd, const BTStep<T>& a, int maxb) {
+        const dim3 g((unsigned)std::max(maxb, 1), (unsigned)ns, chunks);
+#define EH_BT(RBV)                                                                  \
+    if (fwd) hipLaunchKernelGGL((k_bt_fwd<T, RBV>), g, dim3(256), 0, c->s, a);      \
+    else hipLaunchKernelGGL((k_bt_back<T, RBV>), g, dim3(256), 0, c->s, a);
+        if (RB == 8) { EH_BT(8) } else if (RB == 4) { EH_BT(4) } else if (RB == 2) { EH_BT(2) } else { EH_BT(1) }
+#undef EH_BT
+        HIPCHK(hipGetLastError());
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool fwd = pass == 0;
+        for (int k = 0; k < maxnb; ++k) {
+            BTStep<T> a{};
+            a.ns = ns;
+            a.nrhs = nrhs;
+            int maxb = 0;
+            for (int s = 0; s < ns; ++s) {
+                const BTData& bd = c->blk[kinds[s]].btd;
+                const BTPart& pt = bd.pt;
+                const int64_t N = pt.d.np();
+                a.ldy[s] = N;
+                a.f[s] = (const cplx<T>*)f[s];
+                a.vf[s] = vf[s];
+                a.e[s] = (cplx<T>*)out[s];
+                a.ve[s] = vo[s];
+                const int I = fwd ? k : pt.nb - 1 - k;
+                if (k >= pt.nb) {
+                    a.b[s] = 0; a.bo[s] = 0;
+                    a.mat[s] = bd.mats; a.perm[s] = bd.perm; a.y[s] = bd.y; a.yo[s] = bd.y;
+                    continue;
+                }
+                const int J = fwd ? I - 1 : I + 1;
+                a.b[s] = pt.bsize(I);
+                a.bo[s] = pt.bsize(J);
+                a.mat[s] = bd.mats + (fwd ? bd.offF[I] : bd.offB[I]);
+                a.perm[s] = bd.perm + bd.goff[I];
+                a.y[s] = bd.y + bd.goff[I];
+                a.yo[s] = bd.y + ((J >= 0 && J < pt.nb) ? bd.goff[J] : 0);
+                maxb = std::max(maxb, a.b[s]);
+            }
+            launch(fwd, a, maxb);
+        }
+    }
+}
+
 // The fused legs cover 2D V(1, nu2) cycles started from a zero guess.
 inline bool fused_cycle(const eh_ctx* c, bool guess) {
     return c->o.fused && c->dim == 2 && c->o.cycle == 0 && c->o.nu_pre == 1 &&
@@ -883,6 +1113,10 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
     Level* L[GMAX];
     int64_t np[GMAX];
     for (int s = 0; s < ns; ++s) { L[s] = &c->blk[kinds[s]].lev[l]; np[s] = L[s]->d.np(); }
+    if (l == Lv - 1 && c->use_bt) {
+        bt_solve<T>(c, kinds, ns, f, vf, out, vo, nrhs);
+        return;
+    }
     if (l == Lv - 1) {
         GArgs<T> a = gbase<T>(c, kinds, ns, l, false);
         DenseArgs da{};
@@ -1897,6 +2131,7 @@ void eh_default_opts(eh_opts* o) {
     o->autotune = 1;
     o->fused = 1;
     o->ap_variant = 0;
+    o->coarse_solver = 0;
 }
 
 const char* eh_last_error(const eh_ctx* c) {
@@ -1934,6 +2169,9 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
     if (o.autotune != 0 && o.autotune != 1) { g_create_error = "autotune must be 0 or 1"; return EH_ERR_ARG; }
     if (o.fused != 0 && o.fused != 1) { g_create_error = "fused must be 0 or 1"; return EH_ERR_ARG; }
     if (o.ap_variant != 0 && o.ap_variant != 1) { g_create_error = "ap_variant must be 0 or 1"; return EH_ERR_ARG; }
+    if (o.coarse_solver < 0 || o.coarse_solver > 2) {
+        g_create_error = "coarse_solver must be 0 (auto), 1 (dense) or 2 (block-tridiagonal)"; return EH_ERR_ARG;
+    }
     if (!(o.alpha >= 0.0) || !std::isfinite(o.alpha)) { g_create_error = "alpha must be >= 0"; return EH_ERR_ARG; }
     int64_t ncell = 1;
     for (int a = 0; a < dim; ++a) {
@@ -1952,8 +2190,21 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
             return EH_ERR_ARG;
         }
     }
+    // coarsest solver: the dense inverse while every block's coarsest grid
+    // has at most kDenseMax points (auto), else block-tridiagonal
+    int64_t nc_max = 0;
+    for (int b = 0; b <= dim; ++b) {
+        int64_t np = 1;
+        for (int a = 0; a < dim; ++a) np *= (n[a] >> (o.levels - 1)) + (b == a ? 1 : 0);
+        nc_max = std::max(nc_max, np);
+    }
+    if (o.coarse_solver == 1 && nc_max > kDenseMax) {
+        g_create_error = "coarsest grid too large for the dense direct solve (use coarse_solver 0 or 2)";
+        return EH_ERR_ARG;
+    }
     eh_ctx* c = new (std::nothrow) eh_ctx();
     if (!c) { g_create_error = "out of host memory"; return EH_ERR_OOM; }
+    c->use_bt = o.coarse_solver == 2 || (o.coarse_solver == 0 && nc_max > kDenseMax);
     try {
         c->dim = dim;
         for (int a = 0; a < 3; ++a) { c->n[a] = a < dim ? n[a] : 1; c->h[a] = a < dim ? h[a] : 1.0; }
