@@ -31,36 +31,89 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, iters_ref, n_iters):
-    """The oracle (NumPy/SciPy FP64, single thread) on the same workload:
-    setup excluded, `n_iters` FGMRES iterations timed, extrapolated to the
-    GPU's FP64 iteration count."""
-    import numpy as np
+def oracle_iterations(wl):
+    """The oracle's own iteration counts on this workload, from the record
+    tests/golden/make_oracle_iterations.py wrote (None when there is none)."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_iterations_{wl.name}.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != wl.name:
+        return None
+    return rec
+
+
+_CPU = {}
+
+
+def _cpu_sample(q):
+    """n FGMRES iterations of the oracle on source q (forked worker)."""
+    from oracle.fgmres import fgmres
+    H, M, b, wl, n = _CPU["H"], _CPU["M"], _CPU["b"], _CPU["wl"], _CPU["n"]
+    t0 = time.perf_counter()
+    res = fgmres(lambda x: H @ x, M, b[q % b.shape[0]], restart=wl.restart, tol=wl.tol, maxit=n)
+    return (time.perf_counter() - t0) / max(res.iters, 1)
+
+
+def cpu_baseline(wl, n_iters, procs, gpu_fp64_iters=None):
+    """The oracle (NumPy/SciPy FP64, one thread per process) on the same
+    workload: setup once (not timed), then `n_iters` FGMRES iterations
+    timed in one process, and again in `procs` processes forked after the
+    setup, each on its own source (right-hand sides are independent: the
+    RHS-parallel throughput of the host).  Seconds per RHS = seconds per
+    iteration x the oracle's own iteration count on this workload (mean over
+    its sources, tests/golden/oracle_iterations_*.json), or the GPU's FP64
+    count where the oracle has no record (labelled)."""
+    import multiprocessing as mp
+
     from threadpoolctl import threadpool_limits
 
     import workloads as W
     from oracle.elastic import ElasticSystem
-    from oracle.fgmres import fgmres
     from oracle.precond import BlockAcoustic
 
+    rec = oracle_iterations(wl)
+    if rec is not None:
+        iters, iters_src = rec["iters_mean"], (f"the oracle's own count, mean over its {len(rec['sources'])} "
+                                               f"sources ({rec['iters_min']}..{rec['iters_max']}), recorded by "
+                                               f"{rec['script']}")
+    else:
+        iters, iters_src = gpu_fp64_iters, "no oracle record for this workload: the GPU's FP64 iteration count"
     with threadpool_limits(1):
-        s = ElasticSystem(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, wl.abc_width, wl.abc_sides)
-        H = s.H()
-        M = BlockAcoustic(s, alpha=wl.alpha, solver="mg", levels=wl.levels, cycle="V",
-                          nu=wl.nu, damping=wl.damping)
-        b = W.point_source_rhs(wl.n, wl.h, wl.sources)[0]
         t0 = time.perf_counter()
-        res = fgmres(lambda x: H @ x, M, b, restart=wl.restart, tol=wl.tol, maxit=n_iters)
-        dt = time.perf_counter() - t0
-    per_it = dt / max(res.iters, 1)
+        s = ElasticSystem(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, wl.abc_width, wl.abc_sides)
+        _CPU.update(H=s.H(), M=BlockAcoustic(s, alpha=wl.alpha, solver="mg", levels=wl.levels, cycle="V",
+                                             nu=wl.nu, damping=wl.damping, intergrid=wl.intergrid),
+                    b=W.point_source_rhs(wl.n, wl.h, wl.sources), wl=wl, n=n_iters)
+        setup = time.perf_counter() - t0
+        log(f"cpu baseline: oracle setup {setup:.1f} s")
+        t1 = _cpu_sample(0)
+        log(f"cpu baseline: one process {t1:.3f} s per iteration")
+        tp = None
+        if procs > 1:
+            with mp.get_context("fork").Pool(procs) as pool:
+                tp = max(pool.map(_cpu_sample, range(procs), chunksize=1))
+            log(f"cpu baseline: {procs} processes {tp:.3f} s per iteration each")
+    _CPU.clear()
+    if iters is None:
+        return None
+    single = t1 * iters
+    par = tp * iters / procs if tp else single
     return {
-        "value": per_it * iters_ref,
+        "value": par,
         "unit": "s/RHS",
-        "cores": 1,
+        "cores": procs if tp else 1,
         "kind": "oracle",
-        "sample": (f"{res.iters} FGMRES iterations of the oracle (FP64 sparse V-cycles, "
-                   f"setup excluded) on the same workload ({wl.name}), {per_it:.3f} s/iteration, "
-                   f"extrapolated to the GPU FP64 iteration count {iters_ref}"),
+        "sample": (f"the oracle (NumPy/SciPy FP64 sparse V-cycles, MGS FGMRES, splu coarsest; setup "
+                   f"{setup:.0f} s not timed) on the same workload ({wl.name}): {n_iters} FGMRES iterations "
+                   f"timed in one process ({t1:.3f} s/iteration) and in {procs} processes at once, one "
+                   f"source each, one thread each ({tp if tp else t1:.3f} s/iteration, the slowest); "
+                   f"extrapolated to {iters:.2f} iterations per RHS ({iters_src}); value = RHS-parallel "
+                   f"throughput over {procs} processes"),
+        "single_process_s_per_rhs": single,
+        "iterations_per_rhs": iters,
+        "extrapolated": True,
         "host": {"nproc": os.cpu_count(), "cpu": host_cpu_model()},
     }
 
@@ -97,10 +150,10 @@ CLASS_KERNELS = {
     "operator": (("eh::k_op_face<", "eh::k_op_cell<"), ("eh::k_op_cell<",)),   # one H apply = 3 (4) fields
     "distribute": (("eh::k_distribute<",), None),
     "couple": (("eh::k_gcouple<",), None),
-    "dense": (("eh::k_gdense<",), None),
+    "dense": (("eh::k_gdense<", "eh::k_bt_fwd<", "eh::k_bt_back<"), None),
     # every timed multigrid kernel: the V-cycles of the three (four) blocks
     "vcycle": (("eh::k_fdown<", "eh::k_fup<", "eh::k_gdense<", "eh::k_gstencil<", "eh::k_gfine<",
-                "eh::k_gtransfer<"), None),
+                "eh::k_gtransfer<", "eh::k_bt_fwd<", "eh::k_bt_back<"), None),
 }
 CLASS_SOURCES = {
     "krylov": ["paper_2411_15897_amd/csrc/eh_krylov_kernels.h", "paper_2411_15897_amd/csrc/eh_common.h"],
@@ -147,7 +200,7 @@ def sources_sha256(files):
     return h.hexdigest()
 
 
-def pmc_summary(fetch_csv, write_csv, kernel, workload):
+def pmc_summary(fetch_csv, write_csv, kernel, workload, config=None):
     """HBM traffic per timed launch of a kernel class from a FETCH_SIZE and a
     WRITE_SIZE rocprofv3 counter run (KiB per dispatch), each scaled by what
     the same counter reads for the 1 GiB calibration copy of the same run
@@ -185,11 +238,14 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload):
     rec["source_files"] = CLASS_SOURCES.get(kernel, DEFAULT_SOURCES)
     rec["source_sha256"] = sources_sha256(rec["source_files"])
     run = "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp64 --copy-calibration"
+    if config is not None:
+        run += f" --config {config}"
     fdir, wdir = os.path.dirname(fetch_csv), os.path.dirname(write_csv)
     rec["commands"] = [
         f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fdir} -o run -- {run}",
         f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {wdir} -o run -- {run}",
-        f"python3 bench.py --roofline-kernel {kernel} --pmc-summary {fetch_csv} {write_csv}",
+        f"python3 bench.py --roofline-kernel {kernel} --pmc-summary {fetch_csv} {write_csv}"
+        + (f" --config {config}" if config is not None else ""),
     ]
     return rec
 
@@ -243,13 +299,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--restart", type=int, default=None)
-    ap.add_argument("--roofline-kernel", default="vcycle",
+    ap.add_argument("--roofline-kernel", default="fine_up",
                     help="kernel class (or the group vcycle: every multigrid kernel) for the roofline figure")
-    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-procs", type=int, default=None,
+                    help="processes of the RHS-parallel CPU baseline (default: min(16, host threads))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -266,8 +324,8 @@ def main():
         return
     if args.pmc_summary:
         import workloads as W
-        print(json.dumps(pmc_summary(*args.pmc_summary, args.roofline_kernel, W.config(args.config).name),
-                         indent=1))
+        print(json.dumps(pmc_summary(*args.pmc_summary, args.roofline_kernel, W.config(args.config).name,
+                                     args.config), indent=1))
         return
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU only; several GPUs would each take a share of "
@@ -275,11 +333,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
     import workloads as W
-    from paper_2411_15897_amd import ElasticHelmholtz
 
     wl = W.config(args.config)
     if args.levels:
@@ -288,9 +342,23 @@ def main():
         wl.alpha = args.alpha
     if args.restart:
         wl.restart = args.restart
+    b_host = W.point_source_rhs(wl.n, wl.h, wl.sources)
+    nrhs = b_host.shape[0]
+
+    # the CPU baseline first: its worker processes are forked before this
+    # process touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        procs = args.cpu_procs or max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(wl, args.cpu_iters, procs)
+
+    import numpy as np
+    import torch
+
+    from paper_2411_15897_amd import ElasticHelmholtz
+
     dev = torch.device("cuda:0")
-    b = torch.from_numpy(W.point_source_rhs(wl.n, wl.h, wl.sources)).to(dev)
-    nrhs = b.shape[0]
+    b = torch.from_numpy(b_host).to(dev)
 
     def make(prec):
         return ElasticHelmholtz(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, levels=wl.levels,
@@ -298,10 +366,14 @@ def main():
                                 restart=wl.restart, abc_width=wl.abc_width,
                                 abc_sides=wl.abc_sides, intergrid=wl.intergrid)
 
+    all_infos = {"c64": [], "c128": []}
+
     def timed(solver, steps, warmup, kernel=None):
+        x = None
         for w in range(warmup):
-            _, info = solver.solve(b, tol=wl.tol, maxit=5000)
-            log(f"warmup {w}: iters {info[0]['iters']} relres {info[0]['relres_true']:.2e}")
+            x, info = solver.solve(b, tol=wl.tol, maxit=5000)
+            all_infos["c64"].append(info)
+            log(f"warmup {w}: iters {[i['iters'] for i in info]}")
         classes = timer_classes(kernel) if kernel else []
         for k in classes:
             solver.timer_read(k)               # drop anything recorded before
@@ -311,17 +383,18 @@ def main():
         t0 = time.perf_counter()
         infos = []
         for k in range(steps):
-            _, info = solver.solve(b, tol=wl.tol, maxit=5000)
+            x, info = solver.solve(b, tol=wl.tol, maxit=5000)
             infos.append(info)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        all_infos["c64"].extend(infos)
         kt = None
         if classes:
             reads = [solver.timer_read(k) for k in classes]
             kt = tuple(sum(r[i] for r in reads) for i in range(3))
         solver.timer_enable([])
-        log(f"timed {steps} solves in {dt:.3f} s, iters {[i[0]['iters'] for i in infos]}")
-        return dt, infos, kt
+        log(f"timed {steps} solves in {dt:.3f} s, iters {[[i['iters'] for i in inf] for inf in infos]}")
+        return dt, infos, kt, x
 
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)       # 1 GiB
@@ -329,7 +402,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    log(f"workload {wl.name}: n={wl.n} omega={wl.omega:.4f} levels={wl.levels} alpha={wl.alpha}")
+    log(f"workload {wl.name}: n={wl.n} nrhs={nrhs} omega={wl.omega:.4f} levels={wl.levels} alpha={wl.alpha}")
     t_setup = time.perf_counter()
     s32 = make(32)
     torch.cuda.synchronize()
@@ -341,7 +414,8 @@ def main():
     # the solve over the classes
     from paper_2411_15897_amd._native import KERNEL_CLASSES
     s32.timer_enable(list(KERNEL_CLASSES))
-    s32.solve(b, tol=wl.tol, maxit=5000)
+    _, info = s32.solve(b, tol=wl.tol, maxit=5000)
+    all_infos["c64"].append(info)
     for k in KERNEL_CLASSES:
         n_, ms_, by_ = s32.timer_read(k)
         if n_:
@@ -351,60 +425,68 @@ def main():
     s32.timer_enable([])
     log(f"per-class split of one solve: {json.dumps(split)}")
     # value: the solve as it runs (Arnoldi steps replayed from HIP graphs)
-    dt32, inf32, _ = timed(s32, args.steps, args.warmup, None)
+    dt32, inf32, _, x32 = timed(s32, args.steps, args.warmup, None)
     # roofline: the same K solves again with every launch of the roofline
-    # class (default: all V-cycle kernels) bracketed by HIP events on the
-    # solver's stream (plain launches; the kernels are the same, only the
-    # launch path differs)
-    _, _, kt = timed(s32, args.steps, 0, kernel)
-    it32 = inf32[-1][0]["iters"]
-    rel32 = max(i[0]["relres_true"] for i in inf32)
+    # class bracketed by HIP events on the solver's stream (plain launches;
+    # the kernels are the same, only the launch path differs), and of the
+    # whole V-cycle group
+    _, _, kt, _ = timed(s32, args.steps, 0, kernel)
+    kt_v = None
+    if kernel != "vcycle":
+        _, _, kt_v, _ = timed(s32, 1, 0, "vcycle")
     s32.close()
     sec32 = dt32 / (args.steps * nrhs)
+    it32 = [i["iters"] for i in inf32[-1]]
 
     fp64 = None
-    it64 = it32
     if not args.no_fp64:
-        # the plain form: complex128 multigrid, one right-hand side per solve
+        # the plain form: complex128 multigrid, every source solved on its
+        # own, one after the other
         s64 = make(64)
-        if nrhs == 1:
-            dt64, inf64, _ = timed(s64, max(1, min(args.steps, 2)), 1)
-            it64 = inf64[-1][0]["iters"]
-            fp64 = {"form": "complex128 multigrid, single RHS",
-                    "s_per_rhs": dt64 / max(1, min(args.steps, 2)), "iters": it64,
-                    "relres_true": max(i[0]["relres_true"] for i in inf64)}
-        else:
-            sample = list(range(min(nrhs, 2)))
-            s64.solve(b[0:1], tol=wl.tol, maxit=5000)          # warm-up
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            inf64 = [s64.solve(b[q:q + 1], tol=wl.tol, maxit=5000)[1][0] for q in sample]
-            torch.cuda.synchronize()
-            dt64 = time.perf_counter() - t0
-            it64 = max(i["iters"] for i in inf64)
-            fp64 = {"form": f"complex128 multigrid, single RHS, sources solved one at a time "
-                            f"(first {len(sample)} of {nrhs} timed)",
-                    "s_per_rhs": dt64 / len(sample), "iters": it64,
-                    "relres_true": max(i["relres_true"] for i in inf64)}
-            log(f"fp64 single-RHS solves: {dt64 / len(sample):.3f} s per RHS, iters {[i['iters'] for i in inf64]}")
-        fp64["value_speedup"] = fp64["s_per_rhs"] / sec32
+        _, info = s64.solve(b[0:1], tol=wl.tol, maxit=5000)          # warm-up (tuning, graphs)
+        all_infos["c128"].append(info)
+        x64 = torch.empty_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf64 = []
+        for q in range(nrhs):
+            _, info = s64.solve(b[q:q + 1], tol=wl.tol, maxit=5000, x=x64[q:q + 1])
+            inf64.append(info[0])
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t0
+        all_infos["c128"].append(inf64)
         s64.close()
+        errs = [(torch.linalg.vector_norm(x32[q] - x64[q]) / torch.linalg.vector_norm(x64[q])).item()
+                for q in range(nrhs)]
+        fp64 = {"form": f"complex128 multigrid, the {nrhs} sources solved one at a time (all timed)",
+                "s_per_rhs": dt64 / nrhs, "iters": [i["iters"] for i in inf64],
+                "relres_true_max": max(i["relres_true"] for i in inf64),
+                "value_speedup": (dt64 / nrhs) / sec32,
+                "x32_vs_x64_rel_err": {"max": max(errs), "min": min(errs), "per_source": errs}}
+        log(f"fp64 single-RHS solves: {dt64 / nrhs:.4f} s per RHS, iters {fp64['iters']}, "
+            f"max |x32 - x64|/|x64| {max(errs):.2e}")
 
-    launches, ms, nbytes = kt
-    avg_ms = ms / max(launches, 1)
-    achieved = (nbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9 if launches else None
-    roof = {
-        "kernel": kernel,
-        "bound": "hbm",
-        "achieved": achieved,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-        "traffic": recorded_traffic(kernel, wl.name),
-        "launches": launches,
-        "avg_us": avg_ms * 1e3,
-        "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
-    }
+    # validity: every right-hand side of every solve converged below tol
+    flat = [i for k in all_infos for inf in all_infos[k] for i in (inf if isinstance(inf, list) else [inf])]
+    valid = all(i["converged"] and i["relres_true"] < wl.tol for i in flat)
+
+    def roof_of(kt_, name):
+        launches, ms, nbytes = kt_
+        avg_ms = ms / max(launches, 1)
+        achieved = (nbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9 if launches else None
+        return {
+            "kernel": name,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": recorded_traffic(name, wl.name),
+            "launches": launches,
+            "avg_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
+        }
+
     out = {
         "metric": "seconds per RHS to rel. residual 1e-6; V-cycle HBM GB/s vs peak",
         "value": sec32,
@@ -418,18 +500,22 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 multigrid / c128 FGMRES",
         "data": "synthetic",
-        "config": {"workload": wl.name, "grid": list(wl.n), "nrhs": nrhs, "omega": wl.omega,
+        "valid": valid,
+        "config": {"workload": wl.name, "grid": list(wl.n), "nrhs": nrhs, "batched": True, "omega": wl.omega,
                    "levels": wl.levels, "cycle": "V(%d,%d)" % tuple(wl.nu), "alpha": wl.alpha,
-                   "restart": wl.restart, "tol": wl.tol, "iters": it32, "relres_true": rel32},
+                   "intergrid": wl.intergrid, "restart": wl.restart, "tol": wl.tol, "iters": it32,
+                   "relres_true_max": max(i["relres_true"] for inf in inf32 for i in inf)},
         "fp64_plain": fp64,
-        "roofline": roof,
+        "roofline": roof_of(kt, kernel),
+        "roofline_vcycle_group": roof_of(kt_v, "vcycle") if kt_v else None,
         "kernel_split_one_solve": split or None,
         "vcycle_one_solve": vcycle_summary(split_bytes),
+        "cpu_baseline": cpu,
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, it64, args.cpu_iters)
     print(json.dumps(out))
+    if not valid:
+        log("bench.py: a right-hand side did not converge below the tolerance; the line is invalid")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

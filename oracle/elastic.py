@@ -267,3 +267,104 @@ class ElasticSystem:
         if not hasattr(self, "_Ak"):
             self._Ak = [self.A_block(k2) for k2 in range(self.dim)]
         return self._Ak[k]
+
+
+# ----------------------------------------------------------------------------
+# the same operator by array differences (large grids)
+
+def _along(v, a, dim):
+    """numpy axis of grid axis a (x = 0) for arrays stored slowest first."""
+    return dim - 1 - a
+
+
+def _diff_to_cells(v, a, h, dim):
+    """(v_{i+1} - v_i)/h along axis a: nodes -> cells (the 1D D_n)."""
+    ax = _along(v, a, dim)
+    return np.diff(v, axis=ax) / h
+
+
+def _diff_to_nodes(w, a, h, dim):
+    """(w_j - w_{j-1})/h along axis a with w = 0 outside: cells -> nodes
+    (the 1D -D_n^T)."""
+    ax = _along(w, a, dim)
+    pad = [(0, 0)] * w.ndim
+    pad[ax] = (1, 1)
+    return np.diff(np.pad(w, pad), axis=ax) / h
+
+
+def _mean_to(v, nodal, dim):
+    """Arithmetic mean over the existing adjacent cells, from cell values v
+    to the location nodal along the axes in `nodal`."""
+    s = v
+    cnt = np.ones(v.shape)
+    for a in range(dim):
+        if not nodal[a]:
+            continue
+        ax = _along(v, a, dim)
+        pad = [(0, 0)] * v.ndim
+        pad[ax] = (1, 1)
+        sp_, cp_ = np.pad(s, pad), np.pad(cnt, pad)
+        lo = [slice(None)] * v.ndim
+        hi = [slice(None)] * v.ndim
+        lo[ax], hi[ax] = slice(0, -1), slice(1, None)
+        s = sp_[tuple(lo)] + sp_[tuple(hi)]
+        cnt = cp_[tuple(lo)] + cp_[tuple(hi)]
+    return s / cnt
+
+
+def apply_H_stencil(n, h, mu, lam_mu, mass, omega, x):
+    """y = H x for the system of eq. mixed-discretized, evaluated field by
+    field with array differences instead of an assembled matrix (for grids
+    where assembling H is too slow).  mu, lam_mu (= lambda + mu) and mass
+    (= rho (1 - i gamma/w)) are cell arrays of shape reversed(n); x is one
+    flat vector [u_1 | ... | u_d | p].  Same readings as ElasticSystem:
+
+      A_k u_k = sum_a G_a^T diag(mu at G_a's location) G_a u_k
+                - w^2 A_f(mass) u_k,
+      G_a = D along a for a = k (to the cells, mu at the cells),
+      G_a = -D^T along a otherwise (to the edges / nodes nodal along k and
+      a, mu averaged over the existing cells there), zero ghosts;
+      y_k = A_k u_k + grad_k p,  y_p = -div u - p / (lambda + mu).
+    """
+    n = tuple(int(v) for v in n)
+    d = len(n)
+    cell = tuple(reversed(n))
+    mu = np.asarray(mu, dtype=np.float64).reshape(cell)
+    lam_mu = np.asarray(lam_mu, dtype=np.float64).reshape(cell)
+    mass = np.asarray(mass, dtype=np.complex128).reshape(cell)
+    x = np.asarray(x, dtype=np.complex128)
+    shapes = [loc_shape(n, face_nodal(d, k)) for k in range(d)] + [cell]
+    parts, o = [], 0
+    for s in shapes:
+        size = int(np.prod(s))
+        parts.append(x[o:o + size].reshape(s))
+        o += size
+    if o != x.shape[0]:
+        raise ValueError("vector length does not match the grid")
+    u, p = parts[:-1], parts[-1]
+    out = []
+    div = np.zeros(cell, dtype=np.complex128)
+    for k in range(d):
+        acc = np.zeros(shapes[k], dtype=np.complex128)
+        for a in range(d):
+            if a == k:
+                g = _diff_to_cells(u[k], a, h[a], d) * mu
+                acc -= _diff_to_nodes(g, a, h[a], d)          # D^T = -(-D^T)
+            else:
+                g = _diff_to_nodes(u[k], a, h[a], d) * _mean_to(mu, edge_nodal(d, k, a), d)
+                acc -= _diff_to_cells(g, a, h[a], d)          # (-D^T)^T = -D
+        acc -= omega ** 2 * _mean_to(mass, face_nodal(d, k), d) * u[k]
+        acc += _diff_to_nodes(p, k, h[k], d)                   # B_k^T p = grad_k p
+        out.append(acc.ravel())
+        div += _diff_to_cells(u[k], k, h[k], d)
+    out.append((-div - p / lam_mu).ravel())
+    return np.concatenate(out)
+
+
+def medium_arrays(n, h, vp, vs, rho, omega, abc_width, abc_sides, gamma0=0.01 * math.pi):
+    """(mu, lambda + mu, rho (1 - i gamma/w)) at the cells, the inputs of
+    apply_H_stencil, from the velocities and the absorbing layer."""
+    mu, lam_mu = lame_from_velocities(vp, vs, rho)
+    gamma = abc_gamma(tuple(int(v) for v in n), omega, abc_width, abc_sides, gamma0)
+    mass = np.asarray(rho, dtype=np.float64) * (1.0 - 1j * gamma / omega)
+    return mu, lam_mu, mass

@@ -78,7 +78,6 @@ struct BTData {
     c128* mats = nullptr;
     int* perm = nullptr;         // group order -> point index (N)
     c128* y = nullptr;           // FP64 work vector, nrhs_cap * N
-    double bytes = 0.0;          // matrix bytes read by one solve
 };
 
 struct Block {
@@ -566,7 +565,6 @@ void build_bt(eh_ctx* c, Block& B, c128* st, const Widths& w, const Dims& d) {
         T.offB[I] = tot;
         tot += (int64_t)pt.bsize(I) * pt.bsize(I + 1);
     }
-    T.bytes = (double)tot * sizeof(c128);
     T.mats = c->alloc<c128>((size_t)tot);
     {
         std::vector<int> perm((size_t)N);
@@ -936,15 +934,21 @@ void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const i
     const int RB = nrhs >= 5 ? 8 : nrhs >= 3 ? 4 : nrhs;
     const unsigned chunks = (unsigned)((nrhs + RB - 1) / RB);
     int maxnb = 0;
-    double by = 0.0;
-    for (int s = 0; s < ns; ++s) {
-        const BTData& bd = c->blk[kinds[s]].btd;
-        maxnb = std::max(maxnb, bd.pt.nb);
-        const double N = (double)bd.pt.d.np();
-        by += bd.bytes * chunks + N * nrhs * (2.0 * sizeof(cplx<T>) + 4.0 * sizeof(c128));
-    }
-    Timed tm(c, KC_DENSE, by);
+    for (int s = 0; s < ns; ++s) maxnb = std::max(maxnb, c->blk[kinds[s]].btd.pt.nb);
+    // algorithmic bytes of one step: the group's matrix rows once per chunk
+    // of right-hand sides, the vector entries read and written once
+    auto step_bytes = [&](bool fwd, const BTStep<T>& a) {
+        double by = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            const double b = a.b[s], bo = a.bo[s];
+            by += (fwd ? b * (b + bo) : b * bo) * sizeof(c128) * chunks;
+            by += nrhs * (fwd ? b * (sizeof(cplx<T>) + sizeof(c128)) + bo * sizeof(c128)
+                              : b * (sizeof(cplx<T>) + 2.0 * sizeof(c128)) + bo * sizeof(c128));
+        }
+        return by;
+    };
     auto launch = [&](bool fwd, const BTStep<T>& a, int maxb) {
+        Timed tm(c, KC_DENSE, step_bytes(fwd, a));
         const dim3 g((unsigned)std::max(maxb, 1), (unsigned)ns, chunks);
 #define EH_BT(RBV)                                                                  \
     if (fwd) hipLaunchKernelGGL((k_bt_fwd<T, RBV>), g, dim3(256), 0, c->s, a);      \

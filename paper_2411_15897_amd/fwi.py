@@ -19,7 +19,17 @@ import math
 
 import torch
 
-from .solver import ElasticHelmholtz
+from .solver import EhelmError, ElasticHelmholtz
+
+
+def _require_converged(info, what, tol):
+    """A solve that stopped at maxit gives a wrong misfit or gradient:
+    refuse it rather than hand it to autograd."""
+    bad = [q for q, i in enumerate(info) if not i["converged"]]
+    if bad:
+        worst = max(info[q]["relres_true"] for q in bad)
+        raise EhelmError(1, f"{what} solve did not reach tol {tol:g} for sources {bad} "
+                            f"(worst relative residual {worst:.3e})")
 
 
 class ElasticMisfit(torch.autograd.Function):
@@ -37,6 +47,11 @@ class ElasticMisfit(torch.autograd.Function):
         solver = ElasticHelmholtz(n, h, vp.detach().cpu().numpy(), vs.detach().cpu().numpy(),
                                   rho.detach().cpu().numpy(), omega, **g)
         u, info = solver.solve(b, tol=tol, maxit=maxit)
+        try:
+            _require_converged(info, "forward", tol)
+        except EhelmError:
+            solver.close()
+            raise
         phi, adj_rhs = solver.misfit(u, rec, d_obs)
         ctx.solver = solver
         ctx.tol, ctx.maxit = tol, maxit
@@ -51,8 +66,11 @@ class ElasticMisfit(torch.autograd.Function):
         u, adj_rhs = ctx.saved_tensors
         solver = ctx.solver
         w, info = solver.solve(adj_rhs, tol=ctx.tol, maxit=ctx.maxit)
-        gvp, gvs, grho = solver.gradient(u, w)
-        solver.close()
+        try:
+            _require_converged(info, "adjoint", ctx.tol)
+            gvp, gvs, grho = solver.gradient(u, w)
+        finally:
+            solver.close()
         ctx.adjoint_info = info
         scale = grad_phi.to(gvp.device)
         out = [(scale * t).reshape(ctx.shape).to(ctx.device) for t in (gvp, gvs, grho)]

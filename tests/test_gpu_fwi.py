@@ -5,9 +5,10 @@ The layered medium with 16 top sources and receivers every second face
 observed data from the medium with a smoothed 2% perturbation of vp and vs.
 The autograd gradient is checked against central finite differences of the
 same GPU misfit on 10 random directions (relative step 1e-6, complex128
-solves to 1e-12), and against the oracle's gradient with direct solves.
-At the full 512^2 size the same finite-difference check runs on 2
-directions.
+solves to 1e-12), and against the oracle's gradient with direct solves at
+128^2 with all 16 sources.  At the full 512^2 size the same finite-
+difference check runs on 10 directions.  A forward or adjoint solve that
+stops short of its tolerance raises instead of returning a gradient.
 """
 import sys
 
@@ -81,39 +82,47 @@ def test_autograd_gradient_matches_finite_differences(problem):
 
 
 def test_autograd_gradient_matches_oracle(problem):
-    """Same misfit at a 32 x 32 slice of the structure: GPU autograd
-    gradient vs the oracle's (direct solves)."""
+    """The 128 x 128 workload of the finite-difference test (16 sources,
+    64 receivers): the GPU autograd gradient against the oracle's gradient
+    with direct (splu) forward and adjoint solves, to 1e-8 relative."""
     from oracle.fwi import gradient as ogradient
     from paper_2411_15897_amd.fwi import misfit
-    wl = W.config(3, scale=16)                 # 32 x 32
-    n, h = wl.n, wl.h
-    src = wl.sources[:4]
-    recs = sorted(set(wl.receivers))
-    b = W.point_source_rhs(n, h, src)
-    rec = W.receiver_indices(n, recs)
-    rng = np.random.default_rng(3)
-    d_obs = rng.standard_normal((len(src), len(rec))) * 1e-3 + 0j
-    geom = dict(n=n, h=h, omega=wl.omega, levels=2, alpha=0.3, mg_precision=64, restart=20,
-                abc_width=4, abc_sides=wl.abc_sides, tol=1e-13, maxit=2000)
+    wl, geom, b, rec, d_obs = problem
+    g = dict(geom, tol=1e-13, maxit=4000)
     vp = torch.tensor(wl.vp, requires_grad=True)
     vs = torch.tensor(wl.vs, requires_grad=True)
     rho = torch.tensor(wl.rho, requires_grad=True)
-    phi = misfit(vp, vs, rho, geom, torch.from_numpy(b).cuda(), torch.from_numpy(rec).cuda(),
-                 torch.from_numpy(d_obs).cuda())
+    phi = misfit(vp, vs, rho, g, b, rec, d_obs)
     phi.backward()
-    phi_o, (gvp, gvs, grho), _, _ = ogradient(n, h, wl.vp, wl.vs, wl.rho, wl.omega, 4, wl.abc_sides,
-                                              b, rec, d_obs)
+    phi_o, (gvp, gvs, grho), _, _ = ogradient(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, geom["abc_width"],
+                                              wl.abc_sides, b.cpu().numpy(), rec.cpu().numpy(),
+                                              d_obs.cpu().numpy())
+    say(f"  phi gpu {phi.item():.12e} oracle {phi_o:.12e}")
     assert abs(phi.item() - phi_o) <= 1e-9 * abs(phi_o)
     for t, o in ((vp, gvp), (vs, gvs), (rho, grho)):
         a = t.grad.numpy().ravel()
-        assert np.linalg.norm(a - o) <= 1e-8 * np.linalg.norm(o)
+        err = np.linalg.norm(a - o) / np.linalg.norm(o)
+        say(f"  gradient rel err {err:.2e}")
+        assert err <= 1e-8
 
 
+def test_unconverged_solve_raises(problem):
+    """maxit too small for the tolerance: the misfit refuses to return."""
+    from paper_2411_15897_amd.fwi import misfit
+    from paper_2411_15897_amd.solver import EhelmError
+    wl, geom, b, rec, d_obs = problem
+    g = dict(geom, maxit=3)
+    vp, vs, rho = (torch.tensor(m) for m in (wl.vp, wl.vs, wl.rho))
+    with pytest.raises(EhelmError, match="forward solve did not reach tol"):
+        misfit(vp, vs, rho, g, b, rec, d_obs)
+
+
+@pytest.mark.timeout(900)
 def test_gradient_full_size_512_finite_differences():
     """The 512 x 512 FWI workload at full size (16 top sources, 256
     receivers, observed data from the medium with a smoothed 2% perturbation
     of vp and vs, 5 levels, alpha 0.7): the autograd gradient against central
-    finite differences of the same GPU misfit along 2 random directions
+    finite differences of the same GPU misfit along 10 random directions
     (relative step 1e-6; FP64 multigrid, FGMRES(20) to 1e-12 so that the
     differences resolve the derivative)."""
     say("full-size FWI gradient 512^2 x 16")
@@ -143,7 +152,8 @@ def test_gradient_full_size_512_finite_differences():
     say(f"  phi = {phi.item():.6e}, iters {info[0]['iters']}")
     rng = np.random.default_rng(8)
     eps = 1e-6
-    for t in range(2):
+    worst = 0.0
+    for t in range(10):
         dirs = [m * rng.standard_normal(m.shape) for m in (wl.vp, wl.vs, wl.rho)]
         with torch.no_grad():
             def at(sg):
@@ -152,5 +162,7 @@ def test_gradient_full_size_512_finite_differences():
             fd = (at(1.0) - at(-1.0)) / (2 * eps)
         an = sum(float((g.grad.numpy() * d).sum()) for g, d in zip((vp, vs, rho), dirs))
         err = abs(fd - an) / abs(an)
+        worst = max(worst, err)
         say(f"  direction {t}: fd {fd:.10e} adjoint {an:.10e} rel err {err:.2e}")
         assert err <= 1e-5
+    say(f"  worst relative error over 10 directions: {worst:.2e}")

@@ -453,18 +453,22 @@ def test_batched_solve_full_size_2048():
         assert rr < 1e-6
 
 
+@pytest.mark.timeout(600)
 def test_operator_and_solve_full_size_192cube():
-    """At the 192^3 size and settings (4 top sources in one solve, 5 levels,
-    mixed intergrid, V(2,2), alpha 1.0, FGMRES(6), complex64 multigrid): the
-    FP64 operator's rows against the oracle on sub-boxes at both corners,
-    under the top face, through the inclusion and across the absorbing
-    layer (FP64 to 1e-12); every right-hand side converges; and the relative
-    residual of each GPU solution, recomputed here through that operator
-    and reduced on the host, is below 1e-6."""
+    """At the 192^3 size and settings (4 top sources in one solve, 4 levels
+    with the coarsest 24^3 solved block-tridiagonally, mixed intergrid,
+    V(2,2), alpha 1.2, FGMRES(6), complex64 multigrid): the FP64 operator's
+    rows against the oracle on sub-boxes at both corners, under the top
+    face, through the inclusion and across the absorbing layer (FP64 to
+    1e-12); every right-hand side converges; and the true relative residual
+    of each of the 4 GPU solutions, recomputed on the host by the oracle's
+    array-difference H over the whole grid, is below 1e-6."""
     say("full-size operator rows and batched solve 192^3 x 4")
+    from oracle.elastic import apply_H_stencil, medium_arrays
     from oracle_windows import window_rows
     from paper_2411_15897_amd import ElasticHelmholtz
     wl = W.config(5)
+    assert wl.levels == 4
     g = ElasticHelmholtz(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, levels=wl.levels, nu=wl.nu,
                          damping=wl.damping, alpha=wl.alpha, mg_precision=32, restart=wl.restart,
                          abc_width=wl.abc_width, abc_sides=wl.abc_sides, intergrid=wl.intergrid)
@@ -484,15 +488,59 @@ def test_operator_and_solve_full_size_192cube():
     del x, y
     b = W.point_source_rhs(wl.n, wl.h, wl.sources)
     assert b.shape[0] == 4
-    bt = to_dev(b)
-    xs, info = g.solve(bt, tol=1e-6, maxit=2000)
+    xs, info = g.solve(to_dev(b), tol=1e-6, maxit=2000)
     assert all(i["converged"] and i["relres_true"] < 1e-6 for i in info)
-    res = (bt - g.apply_operator(xs)).cpu().numpy()
+    xs = xs.cpu().numpy()
     g.close()
+    mu, lm, mass = medium_arrays(wl.n, wl.h, wl.vp, wl.vs, wl.rho, wl.omega, wl.abc_width, wl.abc_sides)
     for q in range(b.shape[0]):
-        rr = np.linalg.norm(res[q]) / np.linalg.norm(b[q])
-        say(f"  RHS {q}: iters {info[q]['iters']} recomputed relres {rr:.2e}")
+        r = b[q] - apply_H_stencil(wl.n, wl.h, mu, lm, mass, wl.omega, xs[q])
+        rr = np.linalg.norm(r) / np.linalg.norm(b[q])
+        say(f"  RHS {q}: iters {info[q]['iters']} oracle-recomputed relres {rr:.2e} "
+            f"(GPU {info[q]['relres_true']:.2e})")
         assert rr < 1e-6
+
+
+def test_paper_3d_cycle_w22_mixed_parity():
+    """The paper's 3D multigrid setting as one unit (Section 4.5): W(2,2)
+    cycles, damping 0.8/0.8/0.2, the mixed intergrid of eq. tildeRu1, 3
+    levels: every block's cycle against the oracle (FP64, 1e-10), the
+    preconditioner (FP64 1e-10, complex64 multigrid 1e-4), and a solve
+    whose true residual the oracle recomputes below 1e-6 within 2
+    iterations of the oracle's FGMRES with the same cycle."""
+    say("3D W(2,2) + mixed intergrid parity")
+    n, levels, alpha = (16, 16, 16), 3, 0.4
+    nu, damping = (2, 2), (0.8, 0.8, 0.2)
+    kw = dict(levels=levels, alpha=alpha, nu=nu, damping=damping, cycle="W", intergrid="mixed")
+    g64, s = make(n, seed=23, mg_precision=64, **kw)
+    g32, _ = make(n, seed=23, mg_precision=32, **kw)
+    for b in range(4):
+        X = s.H_p(alpha) if b == 3 else s.A_block(b, alpha)
+        nodal = (False,) * 3 if b == 3 else face_nodal(3, b)
+        mg = Hierarchy(X, s.n, nodal, levels, damping=damping, nu=nu, cycle="W", intergrid="mixed")
+        f = crand(X.shape[0], 70 + b)
+        assert rel(g64.block_cycle(b, to_dev(f)).cpu().numpy(), mg(f)) <= 1e-10, b
+    M = BlockAcoustic(s, alpha=alpha, solver="mg", levels=levels, cycle="W", nu=nu, damping=damping,
+                      intergrid="mixed")
+    r = crand((2, s.ndof), 71)
+    z64 = g64.apply_preconditioner(to_dev(r)).cpu().numpy()
+    z32 = g32.apply_preconditioner(to_dev(r)).cpu().numpy()
+    for k in range(2):
+        zo = M.apply(r[k])
+        assert rel(z64[k], zo) <= 1e-10
+        say(f"  complex64 multigrid preconditioner vs FP64 oracle: {rel(z32[k], zo):.2e}")
+        assert rel(z32[k], zo) <= 1e-4
+    bvec = np.zeros((1, s.ndof), dtype=np.complex128)
+    bvec[0, s.face_sizes[0] + s.face_sizes[1] + 8 * 16 * 16 + 8 * 16 + 8] = -1.0
+    x, info = g32.solve(to_dev(bvec), tol=1e-6, maxit=500)
+    H = s.H()
+    rr = np.linalg.norm(bvec[0] - H @ x.cpu().numpy()[0]) / np.linalg.norm(bvec[0])
+    ref = fgmres(lambda v: H @ v, M, bvec[0], restart=20, tol=1e-6, maxit=500)
+    say(f"  gpu iters {info[0]['iters']} oracle iters {ref.iters} oracle-recomputed relres {rr:.2e}")
+    assert info[0]["converged"] and rr < 1e-6
+    assert abs(info[0]["iters"] - ref.iters) <= 2
+    g64.close()
+    g32.close()
 
 
 @pytest.mark.parametrize("intergrid", ["full", "mixed"])

@@ -185,3 +185,26 @@ def test_apply_H_matches_assembled():
                       abc_width=2, abc_sides=W.ABC_ALL[3])
     x = np.random.default_rng(1).standard_normal(s.ndof) * (1 + 0.5j)
     np.testing.assert_allclose(s.apply_H(x), s.H() @ x, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("n,h,sides", [((9, 7), (1.0, 0.8), "all"), ((6, 5, 4), (1.0, 0.8, 1.2), "top"),
+                                       ((3, 8, 2), (0.5, 1.0, 1.0), "all")])
+def test_array_difference_H_matches_assembly(n, h, sides):
+    """The array-difference evaluation of H (large grids) equals the
+    assembled H, whose entries the other pins fix, with a heterogeneous
+    medium and an absorbing layer; and it is complex symmetric on its own
+    (x^T H y = y^T H x), the structure of eq. mixed-discretized."""
+    from oracle.elastic import apply_H_stencil, medium_arrays
+    vp, vs, rho = random_medium(n, 8)
+    dim = len(n)
+    sd = W.ABC_ALL[dim] if sides == "all" else W.abc_all_but_top(dim)
+    s = ElasticSystem(n, h, vp, vs, rho, omega=1.3, abc_width=2, abc_sides=sd)
+    mu, lm, m = medium_arrays(n, h, vp, vs, rho, 1.3, 2, sd)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(s.ndof) + 1j * rng.standard_normal(s.ndof)
+    y = rng.standard_normal(s.ndof) + 1j * rng.standard_normal(s.ndof)
+    Hx = apply_H_stencil(n, h, mu, lm, m, 1.3, x)
+    Hy = apply_H_stencil(n, h, mu, lm, m, 1.3, y)
+    ref = s.H() @ x
+    assert np.linalg.norm(Hx - ref) <= 1e-14 * np.linalg.norm(ref)
+    assert abs(y @ Hx - x @ Hy) <= 1e-13 * np.linalg.norm(Hx) * np.linalg.norm(y)

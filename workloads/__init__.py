@@ -231,8 +231,8 @@ def config(k: int, scale: int = 1) -> Workload:
                (2, (m // 3, 2 * m // 3, 1)), (2, (2 * m // 3, 2 * m // 3, 1))]
         return Workload("config5_layered_192cube", n, h, vp, vs, rho, omega,
                         abc_width=max(12 // scale, 1), abc_sides=abc_all_but_top(3),
-                        sources=src, levels=5, nu=(2, 2),
-                        damping=(0.8, 0.8, 0.2), alpha=1.0, restart=6,
+                        sources=src, levels=4, nu=(2, 2),
+                        damping=(0.8, 0.8, 0.2), alpha=1.2, restart=6,
                         intergrid="mixed")
     raise ValueError(f"unknown config {k}")
 
