@@ -213,6 +213,22 @@ eh_status eh_gradient(eh_ctx *ctx, const void *u, const void *w, int nrhs,
 eh_status eh_misfit(eh_ctx *ctx, const void *u, const int64_t *rec, int nrec,
                     const void *d, int nrhs, void *g, double *phi);
 
+/* eh_misfit for callers that cannot allocate device memory or wait: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same misfit, adjoint right-hand side g and summation order as
+ * eh_misfit (bitwise the same results), with three differences: phi is a
+ * DEVICE pointer to one double, written on the context's stream; the call
+ * only enqueues (no allocation, no synchronisation, no hipMemset: g is
+ * cleared by a kernel); receiver indices are checked on the device, and an
+ * index outside [0, ndof) is skipped and makes *phi NaN.  The per-source
+ * partial sums live in a fixed device array of the library, one per GPU,
+ * 4096 doubles (32 KiB) held until the process ends: nrhs above 4096 is
+ * EH_ERR_ARG.  Every call on one GPU shares that array and overwrites the
+ * entries it uses before reading them; calls that overlap on one GPU (other
+ * streams or contexts) race on it. */
+eh_status eh_misfit_noalloc(eh_ctx *ctx, const void *u, const int64_t *rec, int nrec,
+                            const void *d, int nrhs, void *g, double *phi);
+
 /* Event timing of kernel classes, for measuring achieved bandwidth.
  * Bit c of class_mask selects class c: 0 fine-level Jacobi sweep,
  * 1 fine-level residual, 2 coarse-level (Galerkin stencil) sweeps and

@@ -19,7 +19,7 @@ EXPORTED = [
     "eh_apply_preconditioner", "eh_block_cycle", "eh_block_apply",
     "eh_block_dims", "eh_solve", "eh_gradient", "eh_misfit", "eh_set_stream",
     "eh_destroy", "eh_last_error", "eh_timer_enable", "eh_timer_read",
-    "eh_block_solve", "eh_apply_Z", "eh_power_Z",
+    "eh_block_solve", "eh_apply_Z", "eh_power_Z", "eh_misfit_noalloc",
 ]
 
 KERNEL_CLASSES = {
@@ -89,6 +89,8 @@ def lib():
     L.eh_gradient.restype = i32
     L.eh_misfit.argtypes = [vp, vp, vp, i32, vp, i32, vp, P(dbl)]
     L.eh_misfit.restype = i32
+    L.eh_misfit_noalloc.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp]
+    L.eh_misfit_noalloc.restype = i32
     L.eh_timer_enable.argtypes = [vp, ctypes.c_uint]
     L.eh_timer_enable.restype = i32
     L.eh_timer_read.argtypes = [vp, i32, P(i64), P(dbl), P(dbl)]

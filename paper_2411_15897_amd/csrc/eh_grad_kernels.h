@@ -108,18 +108,30 @@ k_gradient(GradGeom G, const c128* __restrict__ u, const c128* __restrict__ w, i
 // One block per right-hand side; thread 0 walks the receivers in order
 // (duplicates accumulate deterministically).  g (zeroed by the caller)
 // receives conj(P_r^T (P_r u - d)); phi_part[s] = 1/2 ||P_r u_s - d_s||^2.
-__global__ void k_misfit(const c128* __restrict__ u, int64_t vs, const int64_t* __restrict__ rec, int nrec,
-                         const c128* __restrict__ d, c128* __restrict__ g, double* __restrict__ phi_part) {
+// A receiver index outside [0, ndof) is skipped and makes phi_part[s] NaN.
+__global__ void k_misfit(const c128* __restrict__ u, int64_t vs, int64_t ndof, const int64_t* __restrict__ rec,
+                         int nrec, const c128* __restrict__ d, c128* __restrict__ g, double* __restrict__ phi_part) {
     const int s = blockIdx.x;
     if (threadIdx.x != 0) return;
     double acc = 0.0;
+    bool bad = false;
     for (int t = 0; t < nrec; ++t) {
         const int64_t q = rec[t];
+        if (q < 0 || q >= ndof) { bad = true; continue; }
         const c128 res = u[s * vs + q] - d[(int64_t)s * nrec + t];
         acc += cabs2(res);
         g[s * vs + q] = g[s * vs + q] + cconj(res);
     }
-    phi_part[s] = 0.5 * acc;
+    phi_part[s] = bad ? __builtin_nan("") : 0.5 * acc;
+}
+
+// phi = sum of the per-source parts in source order (one thread: the same
+// order as a sequential host sum).
+__global__ void k_misfit_sum(const double* __restrict__ phi_part, int nrhs, double* __restrict__ phi) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int r = 0; r < nrhs; ++r) s += phi_part[r];
+    *phi = s;
 }
 
 }  // namespace eh

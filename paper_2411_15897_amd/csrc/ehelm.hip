@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
@@ -29,7 +30,37 @@
 
 using namespace eh;
 
+// Per-source partial sums of eh_misfit_noalloc, in a fixed array of the
+// library instead of an allocation: each GPU the library runs on holds its
+// own copy until the process ends.  Host code reaches a device's copy only
+// through the address hipGetSymbolAddress returns with that device current
+// (misfit_scratch); the array's name is not a device address on the host.
+#define EH_MISFIT_MAX_SOURCES 4096
+static __device__ __align__(256) double scratch[EH_MISFIT_MAX_SOURCES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// Look up the device address of `scratch` on the current device once (at
+// context creation); returns false if the runtime refuses.
+bool setup_misfit_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return false;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_addr[device]) return true;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return false;
+    g_scratch_addr[device] = (double*)ptr;
+    return true;
+}
+
+double* misfit_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_addr[device];
+}
 
 thread_local std::string g_create_error;
 
@@ -2216,6 +2247,7 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
         c->o = o;
         c->s = (hipStream_t)stream;
         HIPCHK(hipGetDevice(&c->device));
+        if (!setup_misfit_scratch(c->device)) throw HipError{hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)"};
         c->dcell = Dims{{(int)c->n[0], (int)c->n[1], (int)c->n[2]}};
         c->ncell = ncell;
         int64_t acc = 0;

@@ -229,6 +229,18 @@ class ElasticHelmholtz:
                                         _ptr(g), ctypes.byref(phi)))
         return phi.value, g
 
+    def misfit_noalloc(self, u, rec, d, g, phi):
+        """eh_misfit_noalloc: writes g and phi (a one-element float64 CUDA
+        tensor) on the context's stream without allocating or waiting."""
+        nrhs = self._nrhs(u, self.ndof)
+        _check_dev(u, torch.complex128, nrhs * self.ndof, "u")
+        _check_dev(rec, torch.int64, rec.numel(), "rec")
+        _check_dev(d, torch.complex128, nrhs * rec.numel(), "d")
+        _check_dev(g, torch.complex128, nrhs * self.ndof, "g")
+        _check_dev(phi, torch.float64, 1, "phi")
+        self._check(self._lib.eh_misfit_noalloc(self._ctx, _ptr(u), _ptr(rec), rec.numel(), _ptr(d), nrhs,
+                                                _ptr(g), _ptr(phi)))
+
     def timer_enable(self, classes):
         """Select kernel classes (names of _native.KERNEL_CLASSES) to time."""
         mask = 0
