@@ -54,6 +54,9 @@ struct FCfg {
 constexpr FCfg kFDown[] = {{32, 8, 256}, {32, 8, 512}, {16, 8, 256}, {7, 3, 128}};
 constexpr FCfg kFUp[] = {{64, 16, 1024}, {64, 8, 512}, {32, 8, 256}, {16, 8, 128}};
 constexpr int kFCfgs = 4;
+#ifndef EH_UP_PREFETCH
+#define EH_UP_PREFETCH 1
+#endif
 constexpr int FUSE_MAXW = 2;
 // LDS elements: down = staged u0 (support + halo) + residual of the support;
 // up = u~ (tile + 2 halos) + first sweep (tile + 1 halo)
@@ -80,6 +83,16 @@ __device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
     }
     ty = t / gridDim.x;
     tx = t - ty * gridDim.x;
+}
+
+// Barrier for the LDS phases of a leg: orders only the workgroup's LDS
+// accesses.  The legs never read global memory that another thread of the
+// workgroup writes in the same launch, so a right-hand side's output stores
+// (and the next one's prefetched loads) need not complete at the barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // First-sweep factor w / D at point p of level l: stored on coarse levels,
@@ -170,27 +183,99 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
     const int64_t rp = (int64_t)mgy * nx + mgx;
     PointOp<T, FINE, KIND, WX, WY, !FINE && NM != 0 && !MIXED> rop;
     if (rin) rop.load(a, slot, d, mgx, mgy, rp);
+    // The staged points of this thread (NU rounds): the point and its first-
+    // sweep factor w D^-1, computed once for the whole batch.
+    constexpr int NU = (UX * UY + NT - 1) / NT;
+    int up_[NU];                                   // < 0: outside the grid (or the region)
+    cplx<T> usc[NU];
+#pragma unroll
+    for (int it = 0; it < NU; ++it) {
+        const int q = threadIdx.x + it * NT;
+        const int uy = q / UX, ux = q - uy * UX;
+        const int gx = rx0 - WX + ux, gy = ry0 - WY + uy;
+        up_[it] = -1;
+        usc[it] = czero<T>();
+        if (q < UX * UY && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            up_[it] = gy * nx + gx;
+            usc[it] = fuse_sc<T, FINE>(a, slot, up_[it]);
+        }
+    }
+    // Fine level with several support points per thread: their operators
+    // (four couplings and the diagonal each) are held for the whole batch.
+    constexpr bool HOLD = FINE && !ONE_R;
+    constexpr int NR = HOLD ? (RX * RY + NT - 1) / NT : 1;
+    PointOp<T, FINE, KIND, WX, WY, false> hop[NR];
+    int hp[NR], hl[NR];
+    if (HOLD) {
+#pragma unroll
+        for (int it = 0; it < NR; ++it) {
+            const int q = threadIdx.x + it * NT;
+            const int ry = q / RX, rx = q - ry * RX;
+            const int gx = rx0 + rx, gy = ry0 + ry;
+            hp[it] = -1;
+            hl[it] = (ry + WY) * UX + (rx + WX);
+            if (q < RX * RY && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                hp[it] = gy * nx + gx;
+                hop[it].load(a, slot, d, gx, gy, hp[it]);
+            }
+        }
+    }
+    // Fine level: every global load of one right-hand side (the staged
+    // points and the support points' f) is issued together without branches
+    // (a point outside reads element 0 and is zeroed), and the next right-
+    // hand side's while this one is restricted.
+    constexpr int NUF = FINE ? NU : 1, NRF = FINE ? NR : 1;
+    cplx<T> inu[NUF], inr[NRF], in_fr = czero<T>();
+    auto load_in = [&](int r) {
+        const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
+#pragma unroll
+        for (int it = 0; it < NUF; ++it) inu[it] = f[up_[it] >= 0 ? up_[it] : 0];
+        if (HOLD) {
+#pragma unroll
+            for (int it = 0; it < NRF; ++it) inr[it] = f[hp[it] >= 0 ? hp[it] : 0];
+        }
+        in_fr = f[rin ? rp : 0];
+    };
+    if constexpr (FINE) load_in(r0);
     for (int r = r0; r < r1; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
-        const cplx<T> fr = rin ? f[rp] : czero<T>();
-        if (r > r0) __syncthreads();                // LDS of the previous RHS consumed
-#pragma unroll 1
-        for (int it = 0; it < (UX * UY + NT - 1) / NT; ++it) {
-            const int q = threadIdx.x + it * NT;
-            if (q >= UX * UY) break;
-            const int uy = q / UX, ux = q - uy * UX;
-            const int gx = rx0 - WX + ux, gy = ry0 - WY + uy;
-            cplx<T> v = czero<T>();
-            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-                const int64_t p = (int64_t)gy * nx + gx;
-                v = fuse_sc<T, FINE>(a, slot, p) * f[p];
+        cplx<T> fr;
+        cplx<T> fhold[NRF];
+        if constexpr (FINE) {
+            if (!EH_UP_PREFETCH && r > r0) load_in(r);
+            fr = rin ? in_fr : czero<T>();
+#pragma unroll
+            for (int it = 0; it < NRF; ++it) fhold[it] = inr[it];
+            if (r > r0) lds_barrier();                  // LDS of the previous RHS consumed
+#pragma unroll
+            for (int it = 0; it < NU; ++it) {
+                const int q = threadIdx.x + it * NT;
+                if (q >= UX * UY) break;
+                U[q] = up_[it] >= 0 ? usc[it] * inu[it] : czero<T>();
             }
-            U[q] = v;
+            if (EH_UP_PREFETCH && r + 1 < r1) load_in(r + 1);
+            lds_barrier();
+        } else {
+            fr = rin ? f[rp] : czero<T>();
+            if (r > r0) __syncthreads();                // LDS of the previous RHS consumed
+#pragma unroll
+            for (int it = 0; it < NU; ++it) {
+                const int q = threadIdx.x + it * NT;
+                if (q >= UX * UY) break;
+                U[q] = up_[it] >= 0 ? usc[it] * f[up_[it]] : czero<T>();
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (ONE_R) {
             if ((int)threadIdx.x < RX * RY)
                 RR[threadIdx.x] = rin ? fr - rop.template apply<UX>(U, (my_ry + WY) * UX + (my_rx + WX)) : czero<T>();
+        } else if (HOLD) {
+#pragma unroll
+            for (int it = 0; it < NR; ++it) {
+                const int q = threadIdx.x + it * NT;
+                if (q >= RX * RY) break;
+                RR[q] = hp[it] >= 0 ? fhold[it] - hop[it].template apply<UX>(U, hl[it]) : czero<T>();
+            }
         } else {
 #pragma unroll 1
             for (int it = 0; it < (RX * RY + NT - 1) / NT; ++it) {
@@ -209,7 +294,8 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
                 RR[q] = v;
             }
         }
-        __syncthreads();
+        if constexpr (FINE) lds_barrier();
+        else __syncthreads();
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
 #pragma unroll 1
         for (int it = 0; it < (CX * CY + NT - 1) / NT; ++it) {
@@ -319,44 +405,109 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     const int64_t rp = (int64_t)rgy * nx + rgx;
     PointOp<T, FINE, KIND, WX, WY, HALF> rop;
     if (RING_EARLY && ring) rop.load(a, slot, d, rgx, rgy, rp);
+    // The staged points of this thread (NA rounds).  On the fine level
+    // everything that does not depend on the right-hand side -- the point,
+    // its first-sweep factor w D^-1, its interpolation parents and weights --
+    // is computed once here and kept for the whole batch; on coarse levels,
+    // whose wide operators already fill the registers, it is recomputed per
+    // right-hand side.
+    constexpr int NA = (AX * AY + NT - 1) / NT;    // at most 3 rounds
+    constexpr int NH = FINE ? NA : 1;
+    int sp[NH], sc0[NH], sdx[NH], sdy[NH];         // sp < 0: outside the grid (or the region)
+    T sw[NH][4];
+    cplx<T> ssc[NH];
+    auto stage_point = [&](int q, int& p, int& c0, int& dx, int& dy, T* w, cplx<T>& sc) {
+        const int ay = q / AX, ax = q - ay * AX;
+        const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
+        p = -1;
+        c0 = 0; dx = 0; dy = 0;
+        w[0] = w[1] = w[2] = w[3] = T(0);
+        sc = czero<T>();
+        if (q < AX * AY && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            int xi0, xi1, yi0, yi1;
+            float xw0, xw1, yw0, yw1;
+            p1<(NM & 1) != 0>(gx, dc.g[0], xi0, xi1, xw0, xw1);
+            p1<(NM & 2) != 0>(gy, dc.g[1], yi0, yi1, yw0, yw1);
+            p = gy * nx + gx;
+            c0 = yi0 * (int)csy + xi0;
+            dx = xi1 - xi0;
+            dy = (yi1 - yi0) * (int)csy;
+            w[0] = T(yw0) * T(xw0);
+            w[1] = T(yw0) * T(xw1);
+            w[2] = T(yw1) * T(xw0);
+            w[3] = T(yw1) * T(xw1);
+            sc = fuse_sc<T, FINE>(a, slot, p);
+        }
+    };
+    if constexpr (FINE) {
+#pragma unroll
+        for (int it = 0; it < NA; ++it)
+            stage_point(threadIdx.x + it * NT, sp[it], sc0[it], sdx[it], sdy[it], sw[it], ssc[it]);
+    }
+    // Fine level: one right-hand side's staging inputs are loaded together
+    // without branches (a point outside reads element 0 and is zeroed), and,
+    // with EH_UP_PREFETCH, the next right-hand side's while this one sweeps.
+    cplx<T> inf[NH], ine[NH][4], in_fm = czero<T>(), in_fr = czero<T>();
+    auto load_in = [&](int r) {
+        const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
+        const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
+#pragma unroll
+        for (int it = 0; it < NH; ++it) {
+            const cplx<T>* e0 = ec + sc0[it];
+            inf[it] = f[sp[it] >= 0 ? sp[it] : 0];
+            ine[it][0] = e0[0];
+            ine[it][1] = e0[sdx[it]];
+            ine[it][2] = e0[sdy[it]];
+            ine[it][3] = e0[sdy[it] + sdx[it]];
+        }
+        in_fm = f[mine ? mp : 0];
+        in_fr = f[ring ? rp : 0];
+    };
+    if constexpr (FINE) load_in(r0);
     for (int r = r0; r < r1; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
         const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
-        const cplx<T> fmine = mine ? f[mp] : czero<T>();
-        const cplx<T> fring = ring ? f[rp] : czero<T>();
-        if (r > r0) __syncthreads();
-        // u~ = w D^-1 f + P e over region A
-        auto stage = [&](int it) {
-            const int q = threadIdx.x + it * NT;
-            if (q >= AX * AY) return;
-            const int ay = q / AX, ax = q - ay * AX;
-            const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
-            cplx<T> v = czero<T>();
-            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-                const int64_t p = (int64_t)gy * nx + gx;
-                int xi0, xi1, yi0, yi1;
-                float xw0, xw1, yw0, yw1;
-                p1<(NM & 1) != 0>(gx, dc.g[0], xi0, xi1, xw0, xw1);
-                p1<(NM & 2) != 0>(gy, dc.g[1], yi0, yi1, yw0, yw1);
-                const cplx<T> pe = (T(yw0) * T(xw0)) * ec[yi0 * csy + xi0] +
-                                   (T(yw0) * T(xw1)) * ec[yi0 * csy + xi1] +
-                                   (T(yw1) * T(xw0)) * ec[yi1 * csy + xi0] +
-                                   (T(yw1) * T(xw1)) * ec[yi1 * csy + xi1];
-                v = fuse_sc<T, FINE>(a, slot, p) * f[p] + pe;
-            }
-            A[q] = v;
-        };
-        constexpr int NA = (AX * AY + NT - 1) / NT;    // at most 3 rounds
+        cplx<T> fmine, fring;
         if constexpr (FINE) {
-            // few registers per point: all rounds' loads in flight at once
+            if (!EH_UP_PREFETCH && r > r0) load_in(r);
+            fmine = mine ? in_fm : czero<T>();
+            fring = ring ? in_fr : czero<T>();
+            if (r > r0) lds_barrier();
+            // u~ = w D^-1 f + P e over region A
 #pragma unroll
-            for (int it = 0; it < NA; ++it) stage(it);
+            for (int it = 0; it < NA; ++it) {
+                const int q = threadIdx.x + it * NT;
+                if (q >= AX * AY) break;
+                const cplx<T> pe = sw[it][0] * ine[it][0] + sw[it][1] * ine[it][1] + sw[it][2] * ine[it][2] +
+                                   sw[it][3] * ine[it][3];
+                A[q] = sp[it] >= 0 ? ssc[it] * inf[it] + pe : czero<T>();
+            }
+            if (EH_UP_PREFETCH && r + 1 < r1) load_in(r + 1);
+            lds_barrier();
         } else {
+            fmine = mine ? f[mp] : czero<T>();
+            fring = ring ? f[rp] : czero<T>();
+            if (r > r0) __syncthreads();
+            // u~ = w D^-1 f + P e over region A
 #pragma unroll 1
-            for (int it = 0; it < NA; ++it) stage(it);
+            for (int it = 0; it < NA; ++it) {
+                const int q = threadIdx.x + it * NT;
+                if (q >= AX * AY) break;
+                int p, c0, dx, dy;
+                T w[4];
+                cplx<T> sc;
+                stage_point(q, p, c0, dx, dy, w, sc);
+                cplx<T> v = czero<T>();
+                if (p >= 0) {
+                    const cplx<T>* e0 = ec + c0;
+                    const cplx<T> pe = w[0] * e0[0] + w[1] * e0[dx] + w[2] * e0[dy] + w[3] * e0[dy + dx];
+                    v = sc * f[p] + pe;
+                }
+                A[q] = v;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (NU2 == 2) {
             // first sweep on the tile (own point) and on the ring around it
             {
@@ -378,7 +529,8 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
                 }
                 B[rby * BX + rbx] = v;
             }
-            __syncthreads();
+            if constexpr (FINE) lds_barrier();
+            else __syncthreads();
         }
         const cplx<T>* S = NU2 == 2 ? B : A;
         constexpr int SX = NU2 == 2 ? BX : AX;

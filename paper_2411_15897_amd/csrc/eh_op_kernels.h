@@ -1,10 +1,6 @@
 // Elastic operator, distributor and coupling kernels (FP64 inputs).
 //
-//  k_op_face / k_op_cell: y = H x (eq. mixed-discretized).  Rows of u_k:
-//      A_k u_k + B_k^T p with B_k^T p = (p(c) - p(c - e_k)) / h_k at the
-//      k-face between cells c - e_k and c (zero ghost p outside).
-//      Rows of p: B u - C p = -sum_k (u_k(hi face) - u_k(lo face)) / h_k
-//      - p / (lambda + mu).
+//  k_op: y = H x (eq. mixed-discretized), every field in one launch.
 //  k_distribute: t = B r_u - A_p r_p (eq. mixed-distributed) with
 //      A_p r = B B^T (mu r) - w^2 rho (1 - i gamma/w) r (eq. Ap), written in
 //      the multigrid precision.  With rs given, the input of RHS r is
@@ -18,22 +14,6 @@
 
 namespace eh {
 
-// Face (i,j,k) of the k-face grid touches cells with index i_a - 1 and i_a
-// along a = kaxis.  Returns the linear cell index of the cell at offset
-// `off` (0 or -1) along kaxis, or -1 when it lies outside.
-__device__ __forceinline__ int64_t face_cell(const Dims& dc, int kaxis, int i, int j, int k, int off) {
-    int c[3] = {i, j, k};
-    c[kaxis] += off;
-    if (c[kaxis] < 0 || c[kaxis] >= dc.g[kaxis]) return -1;
-    return ((int64_t)c[2] * dc.g[1] + c[1]) * dc.g[0] + c[0];
-}
-
-// Launch: blockDim (64, 4), gridDim (x tiles, y tiles, planes x chunks of
-// the batch); workgroup z takes plane z % planes and right-hand sides
-// [c * rch, min(nrhs, c * rch + rch)) with c = z / planes, so a batch on a
-// small grid is spread over more workgroups (the arithmetic of each
-// right-hand side is unchanged).
-//
 // Residual form (RES), for the FGMRES cycle starts: the launch writes
 // r = b - H x instead of H x and, per right-hand side, one partial sum of
 // |r|^2 per workgroup (a butterfly within each wavefront, then the four
@@ -63,87 +43,118 @@ __device__ __forceinline__ void res_partial(const ResArgs& ra, int r, int kz, do
     __syncthreads();       // sv is reused by the next right-hand side
 }
 
-template <class Tin, int DIM, bool RES>
-__global__ void __launch_bounds__(256)
-k_op_face(Dims d, Dims dc, int kaxis, const double* __restrict__ w0, const double* __restrict__ w1,
-          const double* __restrict__ w2, const c128* __restrict__ D0, const cplx<Tin>* __restrict__ u,
-          const cplx<Tin>* __restrict__ pf, double ihk, c128* __restrict__ y, int nrhs,
-          int64_t vs_in, int64_t vs_out, ResArgs ra, int rch) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z % d.g[2];
-    const int rlo = (blockIdx.z / d.g[2]) * rch, rhi = min(nrhs, rlo + rch);
-    const bool in = i < d.g[0] && j < d.g[1];
-    if (!RES && !in) return;
-    const int64_t sy = d.g[0], sz = (int64_t)d.g[0] * d.g[1];
-    const int64_t p = k * sz + j * sy + i;
-    FineCoef<double, 0, DIM> c;
-    c128 Dp = mk(0.0, 0.0);
-    int64_t chi = -1, clo = -1;
-    if (in) {
-        c.load(d, i, j, k, p, w0, w1, w2, 0.0, 0.0, 0.0);
-        Dp = D0[p];
-        chi = face_cell(dc, kaxis, i, j, k, 0);
-        clo = face_cell(dc, kaxis, i, j, k, -1);
-    }
-    for (int r = rlo; r < rhi; ++r) {
-        c128 yv = mk(0.0, 0.0);
-        if (in) {
-            const cplx<Tin>* ur = u + r * vs_in;
-            const cplx<Tin>* pr = pf + r * vs_in;
-            // off-diagonal sum in FP64
-            c128 s = mk(0.0, 0.0);
-            if (i + 1 < d.g[0]) s = s + c.cp[0] * ccast<double>(ur[p + 1]);
-            if (i > 0) s = s + c.cm[0] * ccast<double>(ur[p - 1]);
-            if (j + 1 < d.g[1]) s = s + c.cp[1] * ccast<double>(ur[p + sy]);
-            if (j > 0) s = s + c.cm[1] * ccast<double>(ur[p - sy]);
-            if (DIM == 3) {
-                if (k + 1 < d.g[2]) s = s + c.cp[2] * ccast<double>(ur[p + sz]);
-                if (k > 0) s = s + c.cm[2] * ccast<double>(ur[p - sz]);
-            }
-            c128 g = mk(0.0, 0.0);
-            if (chi >= 0) g = g + ccast<double>(pr[chi]);
-            if (clo >= 0) g = g - ccast<double>(pr[clo]);
-            yv = Dp * ccast<double>(ur[p]) - s + ihk * g;
-            if (RES) yv = ra.b[r * vs_out + p] - yv;
-            y[r * vs_out + p] = yv;
-        }
-        if (RES) res_partial(ra, r, k, yv.re * yv.re + yv.im * yv.im);
-    }
-}
+// Operator coefficients of one launch: per face field a the couplings of
+// A_a along each axis and its complex diagonal, C = 1/(lambda+mu) at the
+// cells, 1/h per axis.
+struct OpArgs {
+    Dims dc;                     // cells
+    Dims df[3];                  // face grids
+    const double* w[3][3];       // w[a][axis]
+    const c128* D[3];
+    const double* C;
+    double ih[3];
+    int64_t off[4];              // field offsets in a vector
+};
 
+// y = H x (all fields) in one launch over the grid of (n1+1) x (n2+1) (x
+// (n3+1)) points: the thread at (i, j, k) owns the a-face (i, j, k) of every
+// face grid that has it and the cell (i, j, k) if it exists, keeps their
+// coefficients in registers for the whole batch, and loads each right-hand
+// side's u_a around its faces once: the same values give the stencil of A_a
+// and the divergence of its cell.  Rows of u_a: A_a u_a + B_a^T p with
+// B_a^T p = (p(c) - p(c - e_a)) / h_a (zero ghost p); rows of p:
+// -sum_a (u_a(c + e_a) - u_a(c)) / h_a - p / (lambda + mu).
+//
+// Launch: blockDim (64, 4), gridDim (x tiles, y tiles, planes x chunks of the
+// batch); workgroup z takes plane z % planes and right-hand sides
+// [c * rch, min(nrhs, c * rch + rch)) with c = z / planes.
 template <class Tin, int DIM, bool RES>
 __global__ void __launch_bounds__(256)
-k_op_cell(Dims dc, const cplx<Tin>* __restrict__ u0, const cplx<Tin>* __restrict__ u1,
-          const cplx<Tin>* __restrict__ u2, const cplx<Tin>* __restrict__ pf,
-          const double* __restrict__ C, double ih0, double ih1, double ih2, c128* __restrict__ y,
-          int nrhs, int64_t vs_in, int64_t vs_out, ResArgs ra, int rch) {
+k_op(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int nrhs, int64_t vs_in, int64_t vs_out,
+     ResArgs ra, int rch) {
+    const int planes = DIM == 3 ? o.dc.g[2] + 1 : 1;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z % dc.g[2];
-    const int rlo = (blockIdx.z / dc.g[2]) * rch, rhi = min(nrhs, rlo + rch);
-    const bool in = i < dc.g[0] && j < dc.g[1];
-    if (!RES && !in) return;
-    const int64_t p = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
-    // face-grid strides: u0 grid (g0+1, g1, g2), u1 (g0, g1+1, g2), u2 (g0, g1, g2+1)
-    const int64_t f0 = ((int64_t)k * dc.g[1] + j) * (dc.g[0] + 1) + i;
-    const int64_t f1 = ((int64_t)k * (dc.g[1] + 1) + j) * dc.g[0] + i;
-    const int64_t f2 = ((int64_t)k * dc.g[1] + j) * dc.g[0] + i;
-    const int64_t s2 = (int64_t)dc.g[0] * dc.g[1];
-    const double Cp = in ? C[p] : 0.0;
-    for (int r = rlo; r < rhi; ++r) {
-        c128 yv = mk(0.0, 0.0);
-        if (in) {
-            const int64_t o = r * vs_in;
-            c128 div = ih0 * (ccast<double>(u0[o + f0 + 1]) - ccast<double>(u0[o + f0]));
-            div = div + ih1 * (ccast<double>(u1[o + f1 + dc.g[0]]) - ccast<double>(u1[o + f1]));
-            if (DIM == 3) div = div + ih2 * (ccast<double>(u2[o + f2 + s2]) - ccast<double>(u2[o + f2]));
-            const c128 pv = ccast<double>(pf[o + p]);
-            yv = mk(-div.re - Cp * pv.re, -div.im - Cp * pv.im);
-            if (RES) yv = ra.b[r * vs_out + p] - yv;
-            y[r * vs_out + p] = yv;
+    const int k = blockIdx.z % planes;
+    const int rlo = (blockIdx.z / planes) * rch, rhi = min(nrhs, rlo + rch);
+    const int n0 = o.dc.g[0], n1 = o.dc.g[1], n2 = DIM == 3 ? o.dc.g[2] : 1;
+    const bool inx = i <= n0 && j <= n1;
+    if (!RES && !inx) return;
+    const int ci[3] = {i, j, k};
+    const int nn[3] = {n0, n1, n2};
+    bool face[3] = {false, false, false};
+    int64_t fp[3] = {0, 0, 0}, fsy[3] = {0, 0, 0}, fsz[3] = {0, 0, 0};
+    FineCoef<double, 0, DIM> cf[DIM];
+    c128 Dp[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        bool ok = inx;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) if (b != a && ci[b] >= nn[b]) ok = false;
+        face[a] = ok;
+        const Dims& d = o.df[a];
+        fsy[a] = d.g[0];
+        fsz[a] = (int64_t)d.g[0] * d.g[1];
+        fp[a] = k * fsz[a] + j * fsy[a] + i;
+        Dp[a] = mk(0.0, 0.0);
+        if (ok) {
+            cf[a].load(d, i, j, k, fp[a], o.w[a][0], o.w[a][1], o.w[a][2], 0.0, 0.0, 0.0);
+            Dp[a] = o.D[a][fp[a]];
+        } else {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) { cf[a].cp[b] = 0.0; cf[a].cm[b] = 0.0; }
         }
-        if (RES) res_partial(ra, r, k, yv.re * yv.re + yv.im * yv.im);
+    }
+    const bool cell = inx && i < n0 && j < n1 && k < n2;
+    const int64_t csy = n0, csz = (int64_t)n0 * n1;
+    const int64_t pc = k * csz + j * csy + i;
+    const double Cp = cell ? o.C[pc] : 0.0;
+    const int64_t cst[3] = {1, csy, csz};
+    for (int r = rlo; r < rhi; ++r) {
+        const cplx<Tin>* xr = x + r * vs_in;
+        const cplx<Tin>* pr = xr + o.off[DIM];
+        double rr = 0.0;
+        const c128 pcv = cell ? ccast<double>(pr[pc]) : mk(0.0, 0.0);
+        c128 div = mk(0.0, 0.0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            if (!face[a]) continue;
+            const Dims& d = o.df[a];
+            const cplx<Tin>* ur = xr + o.off[a];
+            const int64_t p = fp[a];
+            const c128 uc = ccast<double>(ur[p]);
+            // the +e_a neighbour is the other face of this thread's cell
+            c128 up[3], um[3];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) {
+                const int64_t sb = b == 0 ? 1 : (b == 1 ? fsy[a] : fsz[a]);
+                up[b] = ci[b] + 1 < d.g[b] ? ccast<double>(ur[p + sb]) : mk(0.0, 0.0);
+                um[b] = ci[b] > 0 ? ccast<double>(ur[p - sb]) : mk(0.0, 0.0);
+            }
+            if (cell) div = div + o.ih[a] * (up[a] - uc);
+            c128 s = mk(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) s = s + cf[a].cp[b] * up[b] + cf[a].cm[b] * um[b];
+            // p at the cells on both sides of the face (zero ghost outside)
+            c128 g = ci[a] < nn[a] ? pcv : mk(0.0, 0.0);
+            if (ci[a] > 0) g = g - ccast<double>(pr[pc - cst[a]]);
+            c128 yv = Dp[a] * uc - s + o.ih[a] * g;
+            c128* yo = y + r * vs_out + o.off[a];
+            if (RES) {
+                yv = ra.b[r * vs_out + o.off[a] + p] - yv;
+                rr += yv.re * yv.re + yv.im * yv.im;
+            }
+            yo[p] = yv;
+        }
+        if (cell) {
+            c128 yv = mk(-div.re - Cp * pcv.re, -div.im - Cp * pcv.im);
+            if (RES) {
+                yv = ra.b[r * vs_out + o.off[DIM] + pc] - yv;
+                rr += yv.re * yv.re + yv.im * yv.im;
+            }
+            y[r * vs_out + o.off[DIM] + pc] = yv;
+        }
+        if (RES) res_partial(ra, r, k, rr);
     }
 }
 

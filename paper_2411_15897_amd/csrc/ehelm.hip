@@ -1025,9 +1025,10 @@ void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const i
 }
 
 // The fused legs cover 2D V(1, nu2) cycles started from a zero guess.
+// (The legs index a level's points with 32-bit integers.)
 inline bool fused_cycle(const eh_ctx* c, bool guess) {
     return c->o.fused && c->dim == 2 && c->o.cycle == 0 && c->o.nu_pre == 1 &&
-           (c->o.nu_post == 1 || c->o.nu_post == 2) && !guess;
+           (c->o.nu_post == 1 || c->o.nu_post == 2) && !guess && (c->n[0] + 1) * (c->n[1] + 1) < (1LL << 31);
 }
 
 // One level of a V(1, nu2) cycle from a zero guess with the fused legs:
@@ -1295,7 +1296,9 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
         launch_transfer<T>(c, t, blk, true, nrhs);
         HIPCHK(hipGetLastError());
     }
-    const int ncalls = (c->o.cycle == 1) ? 2 : 1;
+    // W: two calls on level l+1, except when it is the coarsest level, whose
+    // direct solve would give the same result again
+    const int ncalls = (c->o.cycle == 1 && l + 2 < Lv) ? 2 : 1;
     for (int t = 0; t < ncalls; ++t) gcycle<T>(c, kinds, ns, l + 1, cf, vcv, ce, vcv, t > 0, nrhs);
     // prolongation and correction, in place on cur (elementwise)
     {
@@ -1544,59 +1547,41 @@ void maybe_autotune(eh_ctx* c, int nrhs) {
 // ---------------------------------------------------------------------------
 // operator and preconditioner
 
-template <class Tin, bool RES>
-void launch_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs, ResArgs ra) {
-    const cplx<Tin>* X = (const cplx<Tin>*)x;
-    const cplx<Tin>* pf = X + c->off[c->dim];
-    const c128* b = ra.b;
-    // a batch on a small grid is spread over chunks of right-hand sides in z
-    auto chunked = [&](const Dims& d, int& rch) {
-        const dim3 g = grid_of(d);
-        rch = rhs_chunk((int)(g.x * g.y * g.z), 1, nrhs);
-        const int nch = (std::max(nrhs, 1) + rch - 1) / rch;
-        return dim3(g.x, g.y, g.z * (unsigned)nch);
-    };
-    for (int k = 0; k < c->dim; ++k) {
-        const Dims& d = c->dface[k];
-        const dim3 g = grid_of(d);
-        int rch = 1;
-        const dim3 gc = chunked(d, rch);
-        ra.b = RES ? b + c->off[k] : nullptr;
-        if (c->dim == 2)
-            hipLaunchKernelGGL((k_op_face<Tin, 2, RES>), gc, kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
-                               c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
-                               y + c->off[k], nrhs, vx, vy, ra, rch);
-        else
-            hipLaunchKernelGGL((k_op_face<Tin, 3, RES>), gc, kBlock, 0, c->s, d, c->dcell, k, c->k1w[k][0],
-                               c->k1w[k][1], c->k1w[k][2], c->k1D[k], X + c->off[k], pf, 1.0 / c->h[k],
-                               y + c->off[k], nrhs, vx, vy, ra, rch);
-        HIPCHK(hipGetLastError());
-        ra.blk0 += (int)(g.x * g.y * g.z);      // partial sums per plane-grid workgroup
-    }
-    const cplx<Tin>* u2 = c->dim == 3 ? X + c->off[2] : X;
-    ra.b = RES ? b + c->off[c->dim] : nullptr;
-    int rch = 1;
-    const dim3 gc = chunked(c->dcell, rch);
-    if (c->dim == 2)
-        hipLaunchKernelGGL((k_op_cell<Tin, 2, RES>), gc, kBlock, 0, c->s, c->dcell, X + c->off[0],
-                           X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
-                           y + c->off[c->dim], nrhs, vx, vy, ra, rch);
-    else
-        hipLaunchKernelGGL((k_op_cell<Tin, 3, RES>), gc, kBlock, 0, c->s, c->dcell, X + c->off[0],
-                           X + c->off[1], u2, pf, c->C, 1.0 / c->h[0], 1.0 / c->h[1], 1.0 / c->h[2],
-                           y + c->off[c->dim], nrhs, vx, vy, ra, rch);
-    HIPCHK(hipGetLastError());
+// Workgroups of one operator application: the grid of (n1+1) x (n2+1) (x
+// (n3+1)) points that k_op runs on.
+inline dim3 op_grid(const eh_ctx* c) {
+    Dims e = c->dcell;
+    for (int a = 0; a < c->dim; ++a) e.g[a] += 1;
+    return grid_of(e);
+}
+inline int op_blocks(const eh_ctx* c) {
+    const dim3 g = op_grid(c);
+    return (int)(g.x * g.y * g.z);
 }
 
-// workgroups of one operator application (the face grids and the cells)
-inline int op_blocks(const eh_ctx* c) {
-    int nb = 0;
-    for (int k = 0; k < c->dim; ++k) {
-        const dim3 g = grid_of(c->dface[k]);
-        nb += (int)(g.x * g.y * g.z);
+template <class Tin, bool RES>
+void launch_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs, ResArgs ra) {
+    OpArgs o{};
+    o.dc = c->dcell;
+    for (int a = 0; a < 3; ++a) {
+        o.ih[a] = 1.0 / c->h[a];
+        if (a < c->dim) {
+            o.df[a] = c->dface[a];
+            for (int b = 0; b < 3; ++b) o.w[a][b] = c->k1w[a][b];
+            o.D[a] = c->k1D[a];
+        }
     }
-    const dim3 g = grid_of(c->dcell);
-    return nb + (int)(g.x * g.y * g.z);
+    for (int a = 0; a < 4; ++a) o.off[a] = c->off[a];
+    o.C = c->C;
+    // a batch on a small grid is spread over chunks of right-hand sides in z
+    const dim3 g = op_grid(c);
+    const int rch = rhs_chunk((int)(g.x * g.y * g.z), 1, nrhs);
+    const dim3 gc(g.x, g.y, g.z * (unsigned)((std::max(nrhs, 1) + rch - 1) / rch));
+    if (c->dim == 2)
+        hipLaunchKernelGGL((k_op<Tin, 2, RES>), gc, kBlock, 0, c->s, o, (const cplx<Tin>*)x, y, nrhs, vx, vy, ra, rch);
+    else
+        hipLaunchKernelGGL((k_op<Tin, 3, RES>), gc, kBlock, 0, c->s, o, (const cplx<Tin>*)x, y, nrhs, vx, vy, ra, rch);
+    HIPCHK(hipGetLastError());
 }
 
 template <class Tin>
