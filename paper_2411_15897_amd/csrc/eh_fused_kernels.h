@@ -17,7 +17,10 @@
 //             Each workgroup owns a tile of fine points.  u~ = u0 + P e over
 //             the tile plus nu2 stencil widths is staged in LDS; each
 //             damped Jacobi sweep runs from LDS on a region one stencil
-//             width smaller, and the last one writes the tile.
+//             width smaller, and the last one writes the tile.  On the fine
+//             level the coarse correction under the region is staged in LDS
+//             too, and a right-hand side's loads are issued while the
+//             previous one sweeps (up_body_fine).
 //
 // The arithmetic per point is that of the unfused kernels (k_gfine,
 // k_gstencil, k_gtransfer); only the order of summation inside a stencil
@@ -54,9 +57,7 @@ struct FCfg {
 constexpr FCfg kFDown[] = {{32, 8, 256}, {32, 8, 512}, {16, 8, 256}, {7, 3, 128}};
 constexpr FCfg kFUp[] = {{64, 16, 1024}, {64, 8, 512}, {32, 8, 256}, {16, 8, 128}};
 constexpr int kFCfgs = 4;
-#ifndef EH_UP_PREFETCH
-#define EH_UP_PREFETCH 1
-#endif
+
 constexpr int FUSE_MAXW = 2;
 // LDS elements: down = staged u0 (support + halo) + residual of the support;
 // up = u~ (tile + 2 halos) + first sweep (tile + 1 halo)
@@ -222,8 +223,7 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
     }
     // Fine level: every global load of one right-hand side (the staged
     // points and the support points' f) is issued together without branches
-    // (a point outside reads element 0 and is zeroed), and the next right-
-    // hand side's while this one is restricted.
+    // (a point outside reads element 0 and is zeroed).
     constexpr int NUF = FINE ? NU : 1, NRF = FINE ? NR : 1;
     cplx<T> inu[NUF], inr[NRF], in_fr = czero<T>();
     auto load_in = [&](int r) {
@@ -236,13 +236,12 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
         }
         in_fr = f[rin ? rp : 0];
     };
-    if constexpr (FINE) load_in(r0);
     for (int r = r0; r < r1; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
         cplx<T> fr;
         cplx<T> fhold[NRF];
         if constexpr (FINE) {
-            if (!EH_UP_PREFETCH && r > r0) load_in(r);
+            load_in(r);
             fr = rin ? in_fr : czero<T>();
 #pragma unroll
             for (int it = 0; it < NRF; ++it) fhold[it] = inr[it];
@@ -253,7 +252,6 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
                 if (q >= UX * UY) break;
                 U[q] = up_[it] >= 0 ? usc[it] * inu[it] : czero<T>();
             }
-            if (EH_UP_PREFETCH && r + 1 < r1) load_in(r + 1);
             lds_barrier();
         } else {
             fr = rin ? f[rp] : czero<T>();
@@ -356,6 +354,7 @@ k_fdown(GArgs<T> a, int nrhs, int rch) {
 // up leg: a.d = level l, a.dc = level l+1, a.f = f_l (vf), a.u = e_{l+1}
 // (vu), a.out = e_l (vo)
 
+// Coarse levels (stored Galerkin stencils); the fine level has up_body_fine.
 template <class T, bool FINE, int KIND, int WX, int WY, int NM, int NU2, int TX, int TY, int NT, bool HALF>
 __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* lds, int r0, int r1, int tile_x,
                                         int tile_y) {
@@ -405,109 +404,37 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     const int64_t rp = (int64_t)rgy * nx + rgx;
     PointOp<T, FINE, KIND, WX, WY, HALF> rop;
     if (RING_EARLY && ring) rop.load(a, slot, d, rgx, rgy, rp);
-    // The staged points of this thread (NA rounds).  On the fine level
-    // everything that does not depend on the right-hand side -- the point,
-    // its first-sweep factor w D^-1, its interpolation parents and weights --
-    // is computed once here and kept for the whole batch; on coarse levels,
-    // whose wide operators already fill the registers, it is recomputed per
-    // right-hand side.
     constexpr int NA = (AX * AY + NT - 1) / NT;    // at most 3 rounds
-    constexpr int NH = FINE ? NA : 1;
-    int sp[NH], sc0[NH], sdx[NH], sdy[NH];         // sp < 0: outside the grid (or the region)
-    T sw[NH][4];
-    cplx<T> ssc[NH];
-    auto stage_point = [&](int q, int& p, int& c0, int& dx, int& dy, T* w, cplx<T>& sc) {
-        const int ay = q / AX, ax = q - ay * AX;
-        const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
-        p = -1;
-        c0 = 0; dx = 0; dy = 0;
-        w[0] = w[1] = w[2] = w[3] = T(0);
-        sc = czero<T>();
-        if (q < AX * AY && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-            int xi0, xi1, yi0, yi1;
-            float xw0, xw1, yw0, yw1;
-            p1<(NM & 1) != 0>(gx, dc.g[0], xi0, xi1, xw0, xw1);
-            p1<(NM & 2) != 0>(gy, dc.g[1], yi0, yi1, yw0, yw1);
-            p = gy * nx + gx;
-            c0 = yi0 * (int)csy + xi0;
-            dx = xi1 - xi0;
-            dy = (yi1 - yi0) * (int)csy;
-            w[0] = T(yw0) * T(xw0);
-            w[1] = T(yw0) * T(xw1);
-            w[2] = T(yw1) * T(xw0);
-            w[3] = T(yw1) * T(xw1);
-            sc = fuse_sc<T, FINE>(a, slot, p);
-        }
-    };
-    if constexpr (FINE) {
-#pragma unroll
-        for (int it = 0; it < NA; ++it)
-            stage_point(threadIdx.x + it * NT, sp[it], sc0[it], sdx[it], sdy[it], sw[it], ssc[it]);
-    }
-    // Fine level: one right-hand side's staging inputs are loaded together
-    // without branches (a point outside reads element 0 and is zeroed), and,
-    // with EH_UP_PREFETCH, the next right-hand side's while this one sweeps.
-    cplx<T> inf[NH], ine[NH][4], in_fm = czero<T>(), in_fr = czero<T>();
-    auto load_in = [&](int r) {
-        const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
-        const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
-#pragma unroll
-        for (int it = 0; it < NH; ++it) {
-            const cplx<T>* e0 = ec + sc0[it];
-            inf[it] = f[sp[it] >= 0 ? sp[it] : 0];
-            ine[it][0] = e0[0];
-            ine[it][1] = e0[sdx[it]];
-            ine[it][2] = e0[sdy[it]];
-            ine[it][3] = e0[sdy[it] + sdx[it]];
-        }
-        in_fm = f[mine ? mp : 0];
-        in_fr = f[ring ? rp : 0];
-    };
-    if constexpr (FINE) load_in(r0);
     for (int r = r0; r < r1; ++r) {
         const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
         const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
-        cplx<T> fmine, fring;
-        if constexpr (FINE) {
-            if (!EH_UP_PREFETCH && r > r0) load_in(r);
-            fmine = mine ? in_fm : czero<T>();
-            fring = ring ? in_fr : czero<T>();
-            if (r > r0) lds_barrier();
-            // u~ = w D^-1 f + P e over region A
-#pragma unroll
-            for (int it = 0; it < NA; ++it) {
-                const int q = threadIdx.x + it * NT;
-                if (q >= AX * AY) break;
-                const cplx<T> pe = sw[it][0] * ine[it][0] + sw[it][1] * ine[it][1] + sw[it][2] * ine[it][2] +
-                                   sw[it][3] * ine[it][3];
-                A[q] = sp[it] >= 0 ? ssc[it] * inf[it] + pe : czero<T>();
-            }
-            if (EH_UP_PREFETCH && r + 1 < r1) load_in(r + 1);
-            lds_barrier();
-        } else {
-            fmine = mine ? f[mp] : czero<T>();
-            fring = ring ? f[rp] : czero<T>();
-            if (r > r0) __syncthreads();
-            // u~ = w D^-1 f + P e over region A
+        const cplx<T> fmine = mine ? f[mp] : czero<T>();
+        const cplx<T> fring = ring ? f[rp] : czero<T>();
+        if (r > r0) __syncthreads();
+        // u~ = w D^-1 f + P e over region A
 #pragma unroll 1
-            for (int it = 0; it < NA; ++it) {
-                const int q = threadIdx.x + it * NT;
-                if (q >= AX * AY) break;
-                int p, c0, dx, dy;
-                T w[4];
-                cplx<T> sc;
-                stage_point(q, p, c0, dx, dy, w, sc);
-                cplx<T> v = czero<T>();
-                if (p >= 0) {
-                    const cplx<T>* e0 = ec + c0;
-                    const cplx<T> pe = w[0] * e0[0] + w[1] * e0[dx] + w[2] * e0[dy] + w[3] * e0[dy + dx];
-                    v = sc * f[p] + pe;
-                }
-                A[q] = v;
+        for (int it = 0; it < NA; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q >= AX * AY) break;
+            const int ay = q / AX, ax = q - ay * AX;
+            const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
+            cplx<T> v = czero<T>();
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const int64_t p = (int64_t)gy * nx + gx;
+                int xi0, xi1, yi0, yi1;
+                float xw0, xw1, yw0, yw1;
+                p1<(NM & 1) != 0>(gx, dc.g[0], xi0, xi1, xw0, xw1);
+                p1<(NM & 2) != 0>(gy, dc.g[1], yi0, yi1, yw0, yw1);
+                const cplx<T> pe = (T(yw0) * T(xw0)) * ec[yi0 * csy + xi0] +
+                                   (T(yw0) * T(xw1)) * ec[yi0 * csy + xi1] +
+                                   (T(yw1) * T(xw0)) * ec[yi1 * csy + xi0] +
+                                   (T(yw1) * T(xw1)) * ec[yi1 * csy + xi1];
+                v = fuse_sc<T, FINE>(a, slot, p) * f[p] + pe;
             }
-            __syncthreads();
+            A[q] = v;
         }
+        __syncthreads();
         if (NU2 == 2) {
             // first sweep on the tile (own point) and on the ring around it
             {
@@ -529,8 +456,7 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
                 }
                 B[rby * BX + rbx] = v;
             }
-            if constexpr (FINE) lds_barrier();
-            else __syncthreads();
+            __syncthreads();
         }
         const cplx<T>* S = NU2 == 2 ? B : A;
         constexpr int SX = NU2 == 2 ? BX : AX;
@@ -542,11 +468,177 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
     }
 }
 
+// Fine-level up leg.  Per right-hand side: the coarse correction e_{l+1}
+// under the tile's region is staged in LDS (one load per coarse point
+// instead of four per fine point), u~ = w D^-1 f + P e is formed from it,
+// and the sweeps follow; the loads of the next right-hand side (its coarse
+// region, f at the staged points, at the own and the ring point) are issued
+// before this one's first sweep.  Two barriers per right-hand side: the
+// next coarse region is written to LDS while this one sweeps (its readers,
+// the staging of u~, are past the first barrier).
+// LDS: coarse region, u~ region, first-sweep region.
+template <int TX, int TY, int NU2>
+struct FineUpGeom {
+    static constexpr int HX = NU2, HY = NU2;                 // fine operators: half width 1
+    static constexpr int AX = TX + 2 * HX, AY = TY + 2 * HY;
+    static constexpr int BX = TX + 2, BY = TY + 2;
+    static constexpr int CW = (AX + 1) / 2 + 3, CH = (AY + 1) / 2 + 3;
+    static constexpr int LDS = CW * CH + AX * AY + (NU2 == 2 ? BX * BY : 0);
+};
+
+template <class T, int KIND, int NM, int NU2, int TX, int TY, int NT>
+__device__ __forceinline__ void up_body_fine(const GArgs<T>& a, int slot, cplx<T>* lds, int r0, int r1, int tile_x,
+                                             int tile_y) {
+    static_assert(TX * TY == NT, "one tile point per thread");
+    using G = FineUpGeom<TX, TY, NU2>;
+    constexpr int AX = G::AX, AY = G::AY, BX = G::BX, BY = G::BY, CW = G::CW, CH = G::CH;
+    constexpr int HX = G::HX, HY = G::HY;
+    constexpr int RING = BX * BY - TX * TY;
+    static_assert(RING <= NT, "at most one ring point per thread");
+    const Dims d = a.d[slot], dc = a.dc[slot];
+    const int nx = d.g[0], ny = d.g[1];
+    const int tx0 = tile_x * TX, ty0 = tile_y * TY;
+    if (tx0 >= nx || ty0 >= ny) return;           // uniform per workgroup
+    cplx<T>* C = lds;
+    cplx<T>* A = lds + CW * CH;
+    cplx<T>* B = A + AX * AY;
+    // coarse region: parents of every point of the u~ region
+    const int cx0 = ((tx0 - HX) >> 1) - 1, cy0 = ((ty0 - HY) >> 1) - 1;
+    // own tile point and its operator
+    const int my_y = threadIdx.x / TX, my_x = threadIdx.x - my_y * TX;
+    const int mgx = tx0 + my_x, mgy = ty0 + my_y;
+    const bool mine = mgx < nx && mgy < ny;
+    const int mp = mine ? mgy * nx + mgx : 0;
+    PointOp<T, true, KIND, 1, 1, false> op;
+    if (mine) op.load(a, slot, d, mgx, mgy, mp);
+    // ring point of the first sweep (NU2 == 2)
+    int rbx = 0, rby = 0;
+    {
+        const int q = threadIdx.x;
+        if (q < 2 * BX) {
+            const int row = q / BX;
+            rbx = q - row * BX;
+            rby = row < 1 ? row : TY + row;
+        } else {
+            const int q2 = q - 2 * BX;
+            const int row = q2 / 2, cc = q2 - row * 2;
+            rby = 1 + row;
+            rbx = cc < 1 ? cc : TX + cc;
+        }
+    }
+    const int rgx = tx0 - 1 + rbx, rgy = ty0 - 1 + rby;
+    const bool ring = NU2 == 2 && (int)threadIdx.x < RING && rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny;
+    const int rp = ring ? rgy * nx + rgx : 0;
+    PointOp<T, true, KIND, 1, 1, false> rop;
+    if (ring) rop.load(a, slot, d, rgx, rgy, rp);
+    // staged points: point, first-sweep factor, parents in the LDS coarse
+    // region and their weights, for the whole batch
+    constexpr int NA = (AX * AY + NT - 1) / NT;
+    int sp[NA], sl[NA], sdx[NA], sdy[NA];
+    T sw[NA][4];
+    cplx<T> ssc[NA];
+#pragma unroll
+    for (int it = 0; it < NA; ++it) {
+        const int q = threadIdx.x + it * NT;
+        const int ay = q / AX, ax = q - ay * AX;
+        const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
+        sp[it] = -1; sl[it] = 0; sdx[it] = 0; sdy[it] = 0;
+        sw[it][0] = sw[it][1] = sw[it][2] = sw[it][3] = T(0);
+        ssc[it] = czero<T>();
+        if (q < AX * AY && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            int xi0, xi1, yi0, yi1;
+            float xw0, xw1, yw0, yw1;
+            p1<(NM & 1) != 0>(gx, dc.g[0], xi0, xi1, xw0, xw1);
+            p1<(NM & 2) != 0>(gy, dc.g[1], yi0, yi1, yw0, yw1);
+            sp[it] = gy * nx + gx;
+            sl[it] = (yi0 - cy0) * CW + (xi0 - cx0);
+            sdx[it] = xi1 - xi0;
+            sdy[it] = (yi1 - yi0) * CW;
+            sw[it][0] = T(yw0) * T(xw0);
+            sw[it][1] = T(yw0) * T(xw1);
+            sw[it][2] = T(yw1) * T(xw0);
+            sw[it][3] = T(yw1) * T(xw1);
+            ssc[it] = fuse_sc<T, true>(a, slot, sp[it]);
+        }
+    }
+    // coarse region points of this thread
+    constexpr int NC = (CW * CH + NT - 1) / NT;
+    int cpt[NC];
+#pragma unroll
+    for (int it = 0; it < NC; ++it) {
+        const int q = threadIdx.x + it * NT;
+        const int cy = q / CW, cx = q - cy * CW;
+        const int gx = cx0 + cx, gy = cy0 + cy;
+        cpt[it] = (q < CW * CH && gx >= 0 && gx < dc.g[0] && gy >= 0 && gy < dc.g[1]) ? gy * dc.g[0] + gx : -1;
+    }
+    // one right-hand side's inputs, loaded without branches (a point outside
+    // reads element 0 and is zeroed where it is used)
+    cplx<T> vc[NC], vf[NA], vfm, vfr;
+    auto load_in = [&](int r) {
+        const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
+        const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
+#pragma unroll
+        for (int it = 0; it < NC; ++it) vc[it] = ec[cpt[it] >= 0 ? cpt[it] : 0];
+#pragma unroll
+        for (int it = 0; it < NA; ++it) vf[it] = f[sp[it] >= 0 ? sp[it] : 0];
+        vfm = f[mp];
+        vfr = f[rp];
+    };
+    auto store_c = [&]() {
+#pragma unroll
+        for (int it = 0; it < NC; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q < CW * CH) C[q] = cpt[it] >= 0 ? vc[it] : czero<T>();
+        }
+    };
+    load_in(r0);
+    store_c();
+    lds_barrier();
+    for (int r = r0; r < r1; ++r) {
+        cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
+        const cplx<T> fmine = mine ? vfm : czero<T>();
+        const cplx<T> fring = ring ? vfr : czero<T>();
+        cplx<T> fa[NA];
+#pragma unroll
+        for (int it = 0; it < NA; ++it) fa[it] = vf[it];
+        const bool more = r + 1 < r1;
+        if (more) load_in(r + 1);
+        // u~ = w D^-1 f + P e over region A
+#pragma unroll
+        for (int it = 0; it < NA; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q >= AX * AY) break;
+            const cplx<T>* c0 = C + sl[it];
+            const cplx<T> pe = sw[it][0] * c0[0] + sw[it][1] * c0[sdx[it]] + sw[it][2] * c0[sdy[it]] +
+                               sw[it][3] * c0[sdy[it] + sdx[it]];
+            A[q] = sp[it] >= 0 ? ssc[it] * fa[it] + pe : czero<T>();
+        }
+        lds_barrier();
+        if (NU2 == 2) {
+            {
+                const int l = (my_y + 2) * AX + (my_x + 2);
+                B[(my_y + 1) * BX + my_x + 1] = mine ? op.template sweep<AX>(A, l, fmine) : czero<T>();
+            }
+            if ((int)threadIdx.x < RING) {
+                const int l = (rby + 1) * AX + (rbx + 1);
+                B[rby * BX + rbx] = ring ? rop.template sweep<AX>(A, l, fring) : czero<T>();
+            }
+            if (more) store_c();
+            lds_barrier();
+            if (mine) out[mp] = op.template sweep<BX>(B, (my_y + 1) * BX + (my_x + 1), fmine);
+        } else {
+            if (more) store_c();
+            if (mine) out[mp] = op.template sweep<AX>(A, (my_y + 1) * AX + (my_x + 1), fmine);
+            lds_barrier();
+        }
+    }
+}
+
 template <class T, bool FINE, int NU2, int CFG>
 __global__ void __launch_bounds__(kFUp[CFG].threads)
 k_fup(GArgs<T> a, int nrhs, int rch) {
     constexpr int TX = kFUp[CFG].x, TY = kFUp[CFG].y, NT = kFUp[CFG].threads;
-    __shared__ cplx<T> lds[fu_lds(TX, TY)];
+    __shared__ cplx<T> lds[FINE ? FineUpGeom<TX, TY, NU2>::LDS : fu_lds(TX, TY)];
     const int slot = blockIdx.z % a.ns;
     const int r0 = (blockIdx.z / a.ns) * rch, r1 = min(nrhs, r0 + rch);
     const int kind = a.kind[slot];
@@ -554,11 +646,12 @@ k_fup(GArgs<T> a, int nrhs, int rch) {
     xcd_tile(tx, ty);
 #define EH_FU(FI, KI, WX, WY, NM, HF) \
     up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT, HF>(a, slot, lds, r0, r1, tx, ty)
+#define EH_FUF(KI, NM) up_body_fine<T, KI, NM, NU2, TX, TY, NT>(a, slot, lds, r0, r1, tx, ty)
     if (FINE) {
-        if (kind == 2 && a.tilde) EH_FU(true, 2, 1, 1, 0, false);
-        else if (kind == 2) EH_FU(true, 1, 1, 1, 0, false);
-        else if (kind == 0) EH_FU(true, 0, 1, 1, 1, false);
-        else EH_FU(true, 0, 1, 1, 2, false);
+        if (kind == 2 && a.tilde) EH_FUF(2, 0);
+        else if (kind == 2) EH_FUF(1, 0);
+        else if (kind == 0) EH_FUF(0, 1);
+        else EH_FUF(0, 2);
     } else if (a.mixed) {
         if (kind == 2) EH_FU(false, 0, 1, 1, 0, false);
         else if (kind == 0) EH_FU(false, 0, 1, 1, 1, false);
@@ -569,6 +662,7 @@ k_fup(GArgs<T> a, int nrhs, int rch) {
         else if (kind == 0) EH_FU(false, 0, 1, 2, 1, true);
         else EH_FU(false, 0, 2, 1, 2, true);
     }
+#undef EH_FUF
 #undef EH_FU
 }
 
