@@ -255,14 +255,14 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
             lds_barrier();
         } else {
             fr = rin ? f[rp] : czero<T>();
-            if (r > r0) __syncthreads();                // LDS of the previous RHS consumed
+            if (r > r0) lds_barrier();                  // LDS of the previous RHS consumed
 #pragma unroll
             for (int it = 0; it < NU; ++it) {
                 const int q = threadIdx.x + it * NT;
                 if (q >= UX * UY) break;
                 U[q] = up_[it] >= 0 ? usc[it] * f[up_[it]] : czero<T>();
             }
-            __syncthreads();
+            lds_barrier();
         }
         if (ONE_R) {
             if ((int)threadIdx.x < RX * RY)
@@ -292,8 +292,7 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
                 RR[q] = v;
             }
         }
-        if constexpr (FINE) lds_barrier();
-        else __syncthreads();
+        lds_barrier();
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
 #pragma unroll 1
         for (int it = 0; it < (CX * CY + NT - 1) / NT; ++it) {
@@ -411,7 +410,7 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
         cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
         const cplx<T> fmine = mine ? f[mp] : czero<T>();
         const cplx<T> fring = ring ? f[rp] : czero<T>();
-        if (r > r0) __syncthreads();
+        if (r > r0) lds_barrier();
         // u~ = w D^-1 f + P e over region A
 #pragma unroll 1
         for (int it = 0; it < NA; ++it) {
@@ -434,7 +433,7 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
             }
             A[q] = v;
         }
-        __syncthreads();
+        lds_barrier();
         if (NU2 == 2) {
             // first sweep on the tile (own point) and on the ring around it
             {
@@ -456,7 +455,7 @@ __device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* ld
                 }
                 B[rby * BX + rbx] = v;
             }
-            __syncthreads();
+            lds_barrier();
         }
         const cplx<T>* S = NU2 == 2 ? B : A;
         constexpr int SX = NU2 == 2 ? BX : AX;

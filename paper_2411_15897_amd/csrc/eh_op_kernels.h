@@ -158,6 +158,129 @@ k_op(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int nrhs, 
     }
 }
 
+// 2D, several right-hand sides per workgroup: k_op with each right-hand
+// side's inputs staged in LDS.  A workgroup owns OTX x OTY points of the
+// (n1+1) x (n2+1) grid (the same ownership as k_op); per right-hand side it
+// loads the u_1 and u_2 faces of its box plus one point around it and the p
+// cells of its box plus one below and to the left -- every value once,
+// coalesced along x -- into one of two LDS buffers, and the next right-hand
+// side's into registers while this one is computed from LDS: one barrier
+// per right-hand side.  Values outside a field are zero (the zero ghosts of
+// the operator).  Same arithmetic per point as k_op.
+constexpr int OTX = 64, OTY = 4;
+template <class Tin, bool RES>
+__global__ void __launch_bounds__(256)
+k_op2_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int nrhs, int64_t vs_in, int64_t vs_out,
+          ResArgs ra, int rch) {
+    constexpr int UW = OTX + 2, UH = OTY + 2;        // u_a box: [x0-1, x0+OTX] x [y0-1, y0+OTY]
+    constexpr int PW = OTX + 1, PH = OTY + 1;        // p box:   [x0-1, x0+OTX-1] x [y0-1, y0+OTY-1]
+    constexpr int NU = UW * UH, NP = PW * PH, NS = 2 * NU + NP;
+    constexpr int NR = (NS + 255) / 256;
+    __shared__ cplx<Tin> lds[2][NS];
+    const int tid = threadIdx.x;
+    const int tx = tid % OTX, ty = tid / OTX;
+    const int x0 = blockIdx.x * OTX, y0 = blockIdx.y * OTY;
+    const int i = x0 + tx, j = y0 + ty;
+    const int rlo = blockIdx.z * rch, rhi = min(nrhs, rlo + rch);
+    const int n0 = o.dc.g[0], n1 = o.dc.g[1];
+    const bool inx = i <= n0 && j <= n1;
+    // staged entries of this thread: field offset + index, or -1 (zero)
+    int64_t sidx[NR];
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+        const int q = tid + it * 256;
+        int64_t v = -1;
+        if (q < 2 * NU) {
+            const int a = q / NU, e = q - a * NU;
+            const int ey = e / UW, ex = e - ey * UW;
+            const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+            const Dims& d = o.df[a];
+            if (gx >= 0 && gx < d.g[0] && gy >= 0 && gy < d.g[1]) v = o.off[a] + (int64_t)gy * d.g[0] + gx;
+        } else if (q < NS) {
+            const int e = q - 2 * NU;
+            const int ey = e / PW, ex = e - ey * PW;
+            const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+            if (gx >= 0 && gx < n0 && gy >= 0 && gy < n1) v = o.off[2] + (int64_t)gy * n0 + gx;
+        }
+        sidx[it] = v;
+    }
+    // own faces and cell, coefficients for the whole batch
+    bool face[2];
+    int64_t fp[2];
+    FineCoef<double, 0, 2> cf[2];
+    c128 Dp[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const Dims& d = o.df[a];
+        face[a] = inx && (a == 0 ? j < n1 : i < n0);
+        fp[a] = (int64_t)j * d.g[0] + i;
+        Dp[a] = mk(0.0, 0.0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) { cf[a].cp[b] = 0.0; cf[a].cm[b] = 0.0; }
+        if (face[a]) {
+            cf[a].load(d, i, j, 0, fp[a], o.w[a][0], o.w[a][1], o.w[a][2], 0.0, 0.0, 0.0);
+            Dp[a] = o.D[a][fp[a]];
+        }
+    }
+    const bool cell = inx && i < n0 && j < n1;
+    const int64_t pc = (int64_t)j * n0 + i;
+    const double Cp = cell ? o.C[pc] : 0.0;
+    // LDS positions of the own point in the u box (+1, +1) and the p box (+1, +1)
+    const int lu = (ty + 1) * UW + (tx + 1);
+    const int lp = 2 * NU + (ty + 1) * PW + (tx + 1);
+    cplx<Tin> vin[NR];
+    auto load_in = [&](int r) {
+        const cplx<Tin>* xr = x + r * vs_in;
+#pragma unroll
+        for (int it = 0; it < NR; ++it) vin[it] = xr[sidx[it] >= 0 ? sidx[it] : 0];
+    };
+    load_in(rlo);
+    for (int r = rlo; r < rhi; ++r) {
+        cplx<Tin>* S = lds[(r - rlo) & 1];
+#pragma unroll
+        for (int it = 0; it < NR; ++it) {
+            const int q = tid + it * 256;
+            if (q < NS) S[q] = sidx[it] >= 0 ? vin[it] : cplx<Tin>{Tin(0), Tin(0)};
+        }
+        if (r + 1 < rhi) load_in(r + 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        double rr = 0.0;
+        const c128 pcv = ccast<double>(S[lp]);
+        c128 div = mk(0.0, 0.0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (!face[a]) continue;
+            const cplx<Tin>* U = S + a * NU;
+            const c128 uc = ccast<double>(U[lu]);
+            const c128 up[2] = {ccast<double>(U[lu + 1]), ccast<double>(U[lu + UW])};
+            const c128 um[2] = {ccast<double>(U[lu - 1]), ccast<double>(U[lu - UW])};
+            if (cell) div = div + o.ih[a] * (up[a] - uc);
+            c128 sum = mk(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) sum = sum + cf[a].cp[b] * up[b] + cf[a].cm[b] * um[b];
+            // p at the cells on both sides of the face (zero ghost outside)
+            const c128 g = pcv - ccast<double>(S[lp - (a == 0 ? 1 : PW)]);
+            c128 yv = Dp[a] * uc - sum + o.ih[a] * g;
+            if (RES) {
+                yv = ra.b[r * vs_out + o.off[a] + fp[a]] - yv;
+                rr += yv.re * yv.re + yv.im * yv.im;
+            }
+            y[r * vs_out + o.off[a] + fp[a]] = yv;
+        }
+        if (cell) {
+            c128 yv = mk(-div.re - Cp * pcv.re, -div.im - Cp * pcv.im);
+            if (RES) {
+                yv = ra.b[r * vs_out + o.off[2] + pc] - yv;
+                rr += yv.re * yv.re + yv.im * yv.im;
+            }
+            y[r * vs_out + o.off[2] + pc] = yv;
+        }
+        if (RES) res_partial(ra, r, 0, rr);
+    }
+}
+
 // TILDE: the Remark's A~_p r = B A_f(mu) B^T r - w^2 rho (1 - i gamma/w) r,
 // sum over faces of mu_f (r_c - r_nb) / h_a^2 with mu_f the mean over the
 // face's existing cells and r = 0 beyond the boundary.

@@ -210,6 +210,8 @@ struct eh_ctx {
     c128* zbuf = nullptr;         // 2 * ndof: work vectors of the Z(alpha) mat-vec
     c128* zy = nullptr;           // ncell: Z v in the power method
     int64_t tmpT_elems = 0;
+    double* misfit_part = nullptr; // eh_misfit's per-source partial sums (grown as needed)
+    int misfit_cap = 0;
     std::vector<void*> allocs;
     std::string err;
     bool broken = false;
@@ -1158,17 +1160,22 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
         DenseArgs da{};
         da.ns = ns;
         int Nmax = 1;
-        double by = 0.0;
         for (int s = 0; s < ns; ++s) {
             const Block& B = c->blk[kinds[s]];
             da.N[s] = (int)B.Nc;
             da.Ainv[s] = B.Ainv;
             Nmax = std::max(Nmax, da.N[s]);
-            by += (double)B.Nc * B.Nc * sizeof(c128) * ((nrhs + 7) / 8) + 2.0 * B.Nc * nrhs * sizeof(cplx<T>);
         }
-        Timed tm(c, KC_DENSE, by);
         int r = 0;
         while (r < nrhs) {
+            // one timed launch per chunk: the inverse once, the chunk's vectors
+            const int rb = nrhs - r >= 8 ? 8 : nrhs - r >= 4 ? 4 : nrhs - r >= 2 ? 2 : 1;
+            double by = 0.0;
+            for (int s = 0; s < ns; ++s) {
+                const double N = (double)c->blk[kinds[s]].Nc;
+                by += N * N * sizeof(c128) + 2.0 * N * rb * sizeof(cplx<T>);
+            }
+            Timed tm(c, KC_DENSE, by);
             for (int s = 0; s < ns; ++s) {
                 a.f[s] = (const cplx<T>*)f[s] + (int64_t)r * vf[s];
                 a.out[s] = (cplx<T>*)out[s] + (int64_t)r * vo[s];
@@ -1547,11 +1554,13 @@ void maybe_autotune(eh_ctx* c, int nrhs) {
 // ---------------------------------------------------------------------------
 // operator and preconditioner
 
-// Workgroups of one operator application: the grid of (n1+1) x (n2+1) (x
-// (n3+1)) points that k_op runs on.
+// Workgroups of one operator application over the grid of (n1+1) x (n2+1)
+// (x (n3+1)) points: k_op2_lds tiles of OTX x OTY points in 2D, k_op's
+// 64 x 4 blocks per plane in 3D.
 inline dim3 op_grid(const eh_ctx* c) {
     Dims e = c->dcell;
     for (int a = 0; a < c->dim; ++a) e.g[a] += 1;
+    if (c->dim == 2) return dim3((unsigned)((e.g[0] + OTX - 1) / OTX), (unsigned)((e.g[1] + OTY - 1) / OTY), 1);
     return grid_of(e);
 }
 inline int op_blocks(const eh_ctx* c) {
@@ -1578,7 +1587,8 @@ void launch_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrh
     const int rch = rhs_chunk((int)(g.x * g.y * g.z), 1, nrhs);
     const dim3 gc(g.x, g.y, g.z * (unsigned)((std::max(nrhs, 1) + rch - 1) / rch));
     if (c->dim == 2)
-        hipLaunchKernelGGL((k_op<Tin, 2, RES>), gc, kBlock, 0, c->s, o, (const cplx<Tin>*)x, y, nrhs, vx, vy, ra, rch);
+        hipLaunchKernelGGL((k_op2_lds<Tin, RES>), gc, dim3(256), 0, c->s, o, (const cplx<Tin>*)x, y, nrhs, vx, vy, ra,
+                           rch);
     else
         hipLaunchKernelGGL((k_op<Tin, 3, RES>), gc, kBlock, 0, c->s, o, (const cplx<Tin>*)x, y, nrhs, vx, vy, ra, rch);
     HIPCHK(hipGetLastError());

@@ -84,13 +84,13 @@ def test_trace_summary_counts_the_last_solves(tmp_path):
 
 
 def test_recorded_traffic_matches_committed_record():
-    """The committed Krylov record is found for its own workload while its
-    sources are unchanged, and never for another workload or class."""
+    """The committed fine up-leg record is found for its own workload while
+    its sources are unchanged, and never for another workload or class."""
     import workloads as W
-    t = bench.recorded_traffic("krylov", W.config(2).name)
+    t = bench.recorded_traffic("fine_up", W.config(4).name)
     assert t is None or t > 0
-    assert bench.recorded_traffic("krylov", W.config(4).name) is None
-    assert bench.recorded_traffic("no_such_class", W.config(2).name) is None
+    assert bench.recorded_traffic("fine_up", W.config(2).name) is None
+    assert bench.recorded_traffic("no_such_class", W.config(4).name) is None
 
 
 def test_vcycle_summary_sums_bytes_and_time_of_the_multigrid_classes():
