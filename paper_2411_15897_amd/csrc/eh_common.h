@@ -49,6 +49,18 @@ __host__ __device__ __forceinline__ cplx<To> ccast(cplx<Ti> a) { return mk<To>(T
 template <class T>
 __host__ __device__ __forceinline__ cplx<T> czero() { return mk<T>(T(0), T(0)); }
 
+__host__ __device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc + a * b as four explicit fused multiply-adds in a fixed order.  The
+// compiler's own contraction of acc + (a * b) depends on the surrounding
+// code (how often each product is used), so the same stencil could round
+// differently in two inlined copies; fixed fmas give the same bits wherever
+// this is inlined, in four instructions instead of six.
+template <class T>
+__host__ __device__ __forceinline__ cplx<T> cfma(cplx<T> a, cplx<T> b, cplx<T> acc) {
+    return mk<T>(fmat(-a.im, b.im, fmat(a.re, b.re, acc.re)), fmat(a.im, b.re, fmat(a.re, b.im, acc.im)));
+}
+
 // Grid of points of one block on one level: extents per axis (x first).
 struct Dims {
     int g[3];

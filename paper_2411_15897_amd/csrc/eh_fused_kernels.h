@@ -147,13 +147,13 @@ struct PointOp {
         for (int oy = -WY; oy <= WY; ++oy)
 #pragma unroll
             for (int ox = -WX; ox <= WX; ++ox)
-                xu = xu + cf[FINE ? 0 : (oy + WY) * (2 * WX + 1) + (ox + WX)] * S[l + oy * SX + ox];
+                xu = cfma(cf[FINE ? 0 : (oy + WY) * (2 * WX + 1) + (ox + WX)], S[l + oy * SX + ox], xu);
         return xu;
     }
     // one damped Jacobi update u + w D^-1 (f - X u) at local index l
     template <int SX>
     __device__ __forceinline__ cplx<T> sweep(const cplx<T>* S, int l, cplx<T> fp) const {
-        return S[l] + sc * (fp - apply<SX>(S, l));
+        return cfma(sc, fp - apply<SX>(S, l), S[l]);
     }
 };
 
@@ -610,7 +610,7 @@ __device__ __forceinline__ void up_body_fine(const GArgs<T>& a, int slot, cplx<T
             const cplx<T>* c0 = C + sl[it];
             const cplx<T> pe = sw[it][0] * c0[0] + sw[it][1] * c0[sdx[it]] + sw[it][2] * c0[sdy[it]] +
                                sw[it][3] * c0[sdy[it] + sdx[it]];
-            A[q] = sp[it] >= 0 ? ssc[it] * fa[it] + pe : czero<T>();
+            A[q] = sp[it] >= 0 ? cfma(ssc[it], fa[it], pe) : czero<T>();
         }
         lds_barrier();
         if (NU2 == 2) {
@@ -633,11 +633,216 @@ __device__ __forceinline__ void up_body_fine(const GArgs<T>& a, int slot, cplx<T
     }
 }
 
+// Coarse-level up leg (stored Galerkin stencils of half widths WX, WY) on
+// the same plan as the fine one: per right-hand side the coarse correction
+// under the region is staged in LDS, u~ is formed from it with every
+// RHS-independent quantity of a staged point (index, w D^-1, parents and
+// weights) held in registers, and the next right-hand side's loads are in
+// flight during the sweeps; two barriers per right-hand side.  The ring
+// points' operators are staged in LDS once per workgroup when they fit
+// (RING_LDS), else loaded per right-hand side.
+template <class T, int WX, int WY, int NU2, int TX, int TY>
+struct CoarseUpGeom {
+    static constexpr int HX = NU2 * WX, HY = NU2 * WY;
+    static constexpr int AX = TX + 2 * HX, AY = TY + 2 * HY;
+    static constexpr int BX = TX + 2 * WX, BY = TY + 2 * WY;
+    static constexpr int RING = NU2 == 2 ? BX * BY - TX * TY : 0;
+    static constexpr int NST = (2 * WX + 1) * (2 * WY + 1);
+    static constexpr int CW = (AX + 1) / 2 + 3, CH = (AY + 1) / 2 + 3;
+    static constexpr int BASE = CW * CH + AX * AY + (NU2 == 2 ? BX * BY : 0);
+    static constexpr bool RING_LDS = NU2 == 2 && (BASE + NST * RING) * (int)sizeof(cplx<T>) <= 56 * 1024;
+    static constexpr int LDS = BASE + (RING_LDS ? NST * RING : 0);
+};
+
+// Interpolation weights from a code of 2 bits: 0 (1, 0), 1 (3/4, 1/4),
+// 2 (1/2, 1/2), 3 (3/4, 0) -- the values p1 gives.
+__device__ __forceinline__ void wcode(int c, float& w0, float& w1) {
+    w0 = c == 0 ? 1.0f : (c == 2 ? 0.5f : 0.75f);
+    w1 = c == 1 ? 0.25f : (c == 2 ? 0.5f : 0.0f);
+}
+__device__ __forceinline__ int wcode_of(float w0, float w1) {
+    return w0 == 1.0f ? 0 : (w0 == 0.5f ? 2 : (w1 == 0.25f ? 1 : 3));
+}
+
+template <class T, int WX, int WY, int NM, int NU2, int TX, int TY, int NT, bool HALF>
+__device__ __forceinline__ void up_body_coarse(const GArgs<T>& a, int slot, cplx<T>* lds, int r0, int r1,
+                                               int tile_x, int tile_y) {
+    static_assert(TX * TY == NT, "one tile point per thread");
+    using G = CoarseUpGeom<T, WX, WY, NU2, TX, TY>;
+    static_assert(G::LDS <= std::max(std::max(CoarseUpGeom<T, 2, 2, NU2, TX, TY>::LDS,
+                                              CoarseUpGeom<T, 1, 2, NU2, TX, TY>::LDS),
+                                     std::max(CoarseUpGeom<T, 2, 1, NU2, TX, TY>::LDS,
+                                              CoarseUpGeom<T, 1, 1, NU2, TX, TY>::LDS)),
+                  "the kernel's LDS array covers this stencil shape");
+    constexpr int AX = G::AX, AY = G::AY, BX = G::BX, BY = G::BY, CW = G::CW, CH = G::CH;
+    constexpr int HX = G::HX, HY = G::HY, RING = G::RING, NST = G::NST;
+    constexpr bool RING_LDS = G::RING_LDS;
+    static_assert(RING <= NT, "at most one ring point per thread");
+    const Dims d = a.d[slot], dc = a.dc[slot];
+    const int nx = d.g[0], ny = d.g[1];
+    const int tx0 = tile_x * TX, ty0 = tile_y * TY;
+    if (tx0 >= nx || ty0 >= ny) return;           // uniform per workgroup
+    cplx<T>* C = lds;
+    cplx<T>* A = C + CW * CH;
+    cplx<T>* B = A + AX * AY;
+    cplx<T>* RC = B + (NU2 == 2 ? BX * BY : 0);
+    const int cx0 = ((tx0 - HX) >> 1) - 1, cy0 = ((ty0 - HY) >> 1) - 1;
+    const int my_y = threadIdx.x / TX, my_x = threadIdx.x - my_y * TX;
+    const int mgx = tx0 + my_x, mgy = ty0 + my_y;
+    const bool mine = mgx < nx && mgy < ny;
+    const int mp = mine ? mgy * nx + mgx : 0;
+    PointOp<T, false, 0, WX, WY, HALF> op;
+    if (mine) op.load(a, slot, d, mgx, mgy, mp);
+    // ring point of the first sweep
+    int rbx = 0, rby = 0;
+    {
+        const int q = threadIdx.x;
+        if (q < 2 * WY * BX) {
+            const int row = q / BX;
+            rbx = q - row * BX;
+            rby = row < WY ? row : TY + row;
+        } else {
+            const int q2 = q - 2 * WY * BX;
+            const int row = q2 / (2 * WX), cc = q2 - row * (2 * WX);
+            rby = WY + row;
+            rbx = cc < WX ? cc : TX + cc;
+        }
+    }
+    const int rgx = tx0 - WX + rbx, rgy = ty0 - WY + rby;
+    const bool ring = NU2 == 2 && (int)threadIdx.x < RING && rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny;
+    const int rp = ring ? rgy * nx + rgx : 0;
+    cplx<T> rsc = czero<T>();
+    if (RING_LDS && (int)threadIdx.x < RING) {
+        const int64_t np = d.np();
+#pragma unroll
+        for (int o = 0; o < NST; ++o) {
+            const int oy = o / (2 * WX + 1) - WY, ox = o % (2 * WX + 1) - WX;
+            const bool ok = ring && (!HALF || o >= NST / 2 ||
+                                     (rgx + ox >= 0 && rgx + ox < nx && rgy + oy >= 0 && rgy + oy < ny));
+            RC[o * RING + threadIdx.x] = ok ? stencil_coef<T, NST, HALF>(a.coef[slot], np, o, rp, rp + oy * nx + ox)
+                                            : czero<T>();
+        }
+        rsc = ring ? a.dinv[slot][rp] : czero<T>();
+    }
+    // staged points: index, w D^-1, parents in the LDS coarse region and the
+    // weight codes, for the whole batch
+    constexpr int NA = (AX * AY + NT - 1) / NT;
+    int sp[NA], sl[NA], sk[NA];
+    cplx<T> ssc[NA];
+#pragma unroll
+    for (int it = 0; it < NA; ++it) {
+        const int q = threadIdx.x + it * NT;
+        const int ay = q / AX, ax = q - ay * AX;
+        const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
+        sp[it] = -1; sl[it] = 0; sk[it] = 0;
+        ssc[it] = czero<T>();
+        if (q < AX * AY && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            int xi0, xi1, yi0, yi1;
+            float xw0, xw1, yw0, yw1;
+            p1<(NM & 1) != 0>(gx, dc.g[0], xi0, xi1, xw0, xw1);
+            p1<(NM & 2) != 0>(gy, dc.g[1], yi0, yi1, yw0, yw1);
+            sp[it] = gy * nx + gx;
+            sl[it] = (yi0 - cy0) * CW + (xi0 - cx0);
+            // bits 0-1 / 2-3: weight codes along x / y; bits 4-5 / 6-7: parent step + 1
+            sk[it] = wcode_of(xw0, xw1) | (wcode_of(yw0, yw1) << 2) | ((xi1 - xi0 + 1) << 4) | ((yi1 - yi0 + 1) << 6);
+            ssc[it] = a.dinv[slot][sp[it]];
+        }
+    }
+    constexpr int NC = (CW * CH + NT - 1) / NT;
+    int cpt[NC];
+#pragma unroll
+    for (int it = 0; it < NC; ++it) {
+        const int q = threadIdx.x + it * NT;
+        const int cy = q / CW, cx = q - cy * CW;
+        const int gx = cx0 + cx, gy = cy0 + cy;
+        cpt[it] = (q < CW * CH && gx >= 0 && gx < dc.g[0] && gy >= 0 && gy < dc.g[1]) ? gy * dc.g[0] + gx : -1;
+    }
+    cplx<T> vc[NC], vf[NA], vfm, vfr;
+    auto load_in = [&](int r) {
+        const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
+        const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
+#pragma unroll
+        for (int it = 0; it < NC; ++it) vc[it] = ec[cpt[it] >= 0 ? cpt[it] : 0];
+#pragma unroll
+        for (int it = 0; it < NA; ++it) vf[it] = f[sp[it] >= 0 ? sp[it] : 0];
+        vfm = f[mp];
+        vfr = f[rp];
+    };
+    auto store_c = [&]() {
+#pragma unroll
+        for (int it = 0; it < NC; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q < CW * CH) C[q] = cpt[it] >= 0 ? vc[it] : czero<T>();
+        }
+    };
+    load_in(r0);
+    store_c();
+    lds_barrier();
+    for (int r = r0; r < r1; ++r) {
+        cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
+        const cplx<T> fmine = mine ? vfm : czero<T>();
+        const cplx<T> fring = ring ? vfr : czero<T>();
+        cplx<T> fa[NA];
+#pragma unroll
+        for (int it = 0; it < NA; ++it) fa[it] = vf[it];
+        const bool more = r + 1 < r1;
+        if (more) load_in(r + 1);
+#pragma unroll
+        for (int it = 0; it < NA; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q >= AX * AY) break;
+            float xw0, xw1, yw0, yw1;
+            wcode(sk[it] & 3, xw0, xw1);
+            wcode((sk[it] >> 2) & 3, yw0, yw1);
+            const int dx = ((sk[it] >> 4) & 3) - 1, dy = (((sk[it] >> 6) & 3) - 1) * CW;
+            const cplx<T>* c0 = C + sl[it];
+            const cplx<T> pe = (T(yw0) * T(xw0)) * c0[0] + (T(yw0) * T(xw1)) * c0[dx] + (T(yw1) * T(xw0)) * c0[dy] +
+                               (T(yw1) * T(xw1)) * c0[dy + dx];
+            A[q] = sp[it] >= 0 ? cfma(ssc[it], fa[it], pe) : czero<T>();
+        }
+        lds_barrier();
+        if (NU2 == 2) {
+            B[(my_y + WY) * BX + my_x + WX] =
+                mine ? op.template sweep<AX>(A, (my_y + 2 * WY) * AX + (my_x + 2 * WX), fmine) : czero<T>();
+            if ((int)threadIdx.x < RING) {
+                const int l = (rby + WY) * AX + (rbx + WX);
+                cplx<T> v = czero<T>();
+                if (ring && RING_LDS) {
+                    // the same PointOp code as every other point, fed from LDS
+                    PointOp<T, false, 0, WX, WY, HALF> wop;
+#pragma unroll
+                    for (int o = 0; o < NST; ++o) wop.cf[o] = RC[o * RING + threadIdx.x];
+                    wop.sc = rsc;
+                    v = wop.template sweep<AX>(A, l, fring);
+                } else if (ring) {
+                    PointOp<T, false, 0, WX, WY, HALF> wop;
+                    wop.load(a, slot, d, rgx, rgy, rp);
+                    v = wop.template sweep<AX>(A, l, fring);
+                }
+                B[rby * BX + rbx] = v;
+            }
+            if (more) store_c();
+            lds_barrier();
+            if (mine) out[mp] = op.template sweep<BX>(B, (my_y + WY) * BX + (my_x + WX), fmine);
+        } else {
+            if (more) store_c();
+            if (mine) out[mp] = op.template sweep<AX>(A, (my_y + HY) * AX + (my_x + HX), fmine);
+            lds_barrier();
+        }
+    }
+}
+
 template <class T, bool FINE, int NU2, int CFG>
 __global__ void __launch_bounds__(kFUp[CFG].threads)
 k_fup(GArgs<T> a, int nrhs, int rch) {
     constexpr int TX = kFUp[CFG].x, TY = kFUp[CFG].y, NT = kFUp[CFG].threads;
-    __shared__ cplx<T> lds[FINE ? FineUpGeom<TX, TY, NU2>::LDS : fu_lds(TX, TY)];
+    // every stencil shape the coarse levels use: 5x5, 3x5, 5x3, 3x3
+    constexpr int LDS_N = FINE ? FineUpGeom<TX, TY, NU2>::LDS
+                               : std::max(std::max(CoarseUpGeom<T, 2, 2, NU2, TX, TY>::LDS,
+                                                   CoarseUpGeom<T, 1, 2, NU2, TX, TY>::LDS),
+                                          std::max(CoarseUpGeom<T, 2, 1, NU2, TX, TY>::LDS,
+                                                   CoarseUpGeom<T, 1, 1, NU2, TX, TY>::LDS));
+    __shared__ cplx<T> lds[LDS_N];
     const int slot = blockIdx.z % a.ns;
     const int r0 = (blockIdx.z / a.ns) * rch, r1 = min(nrhs, r0 + rch);
     const int kind = a.kind[slot];
@@ -646,21 +851,23 @@ k_fup(GArgs<T> a, int nrhs, int rch) {
 #define EH_FU(FI, KI, WX, WY, NM, HF) \
     up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT, HF>(a, slot, lds, r0, r1, tx, ty)
 #define EH_FUF(KI, NM) up_body_fine<T, KI, NM, NU2, TX, TY, NT>(a, slot, lds, r0, r1, tx, ty)
+#define EH_FUC(WX, WY, NM, HF) up_body_coarse<T, WX, WY, NM, NU2, TX, TY, NT, HF>(a, slot, lds, r0, r1, tx, ty)
     if (FINE) {
         if (kind == 2 && a.tilde) EH_FUF(2, 0);
         else if (kind == 2) EH_FUF(1, 0);
         else if (kind == 0) EH_FUF(0, 1);
         else EH_FUF(0, 2);
     } else if (a.mixed) {
-        if (kind == 2) EH_FU(false, 0, 1, 1, 0, false);
-        else if (kind == 0) EH_FU(false, 0, 1, 1, 1, false);
-        else EH_FU(false, 0, 1, 1, 2, false);
+        if (kind == 2) EH_FUC(1, 1, 0, false);
+        else if (kind == 0) EH_FUC(1, 1, 1, false);
+        else EH_FUC(1, 1, 2, false);
     } else {
         // full weighting: the shear blocks' stencils are stored half
-        if (kind == 2) EH_FU(false, 0, 2, 2, 0, false);
-        else if (kind == 0) EH_FU(false, 0, 1, 2, 1, true);
-        else EH_FU(false, 0, 2, 1, 2, true);
+        if (kind == 2) EH_FUC(2, 2, 0, false);
+        else if (kind == 0) EH_FUC(1, 2, 1, true);
+        else EH_FUC(2, 1, 2, true);
     }
+#undef EH_FUC
 #undef EH_FUF
 #undef EH_FU
 }
