@@ -96,6 +96,12 @@ typedef struct {
                                   one launch per group; the factors are checked at create by one solve
                                   whose FP64 residual must stay below 1e-8 (EH_ERR_ARG otherwise);
                                0: 1 while every block's coarsest grid has at most 6000 points, else 2 */
+    int drop_converged;     /* 1: at each FGMRES restart, right-hand sides whose true residual is below tol
+                               leave the batch -- the others are gathered into the first slots and every
+                               later launch covers only them (two ndof-vectors per remaining right-hand side
+                               are allocated at the first such restart and freed before eh_solve returns);
+                               per right-hand side the arithmetic, the result and the iteration count are
+                               the same as with 0, where every launch covers the whole batch */
 } eh_opts;
 
 typedef struct {

@@ -39,7 +39,7 @@ class EhOpts(ctypes.Structure):
         ("abc_sides", ctypes.c_uint), ("gamma0", ctypes.c_double),
         ("intergrid", ctypes.c_int), ("graphs", ctypes.c_int),
         ("autotune", ctypes.c_int), ("fused", ctypes.c_int), ("ap_variant", ctypes.c_int),
-        ("coarse_solver", ctypes.c_int),
+        ("coarse_solver", ctypes.c_int), ("drop_converged", ctypes.c_int),
     ]
 
 

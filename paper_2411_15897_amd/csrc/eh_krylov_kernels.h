@@ -396,6 +396,32 @@ k_arn_givens(ArnState s, int j, const c128* __restrict__ nrm, ArnStatus* out) {
     out[r] = st;
 }
 
+// A cycle start that drops finished right-hand sides from the batch: slot i
+// takes the state of slot map[i] (map increasing, so map[i] >= i and one
+// thread moving the slots in order never overwrites a slot it has still to
+// read).  What moves is the state that outlives a cycle (the norm of b, the
+// estimate, the counts and flags) and the entries k_arn_start has just
+// written for the new cycle (scales, rotated right-hand side).
+__global__ void __launch_bounds__(64)
+k_arn_compact(ArnState s, const int* __restrict__ map, int k) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int m = s.m;
+    for (int i = 0; i < k; ++i) {
+        const int q = map[i];
+        if (q == i) continue;
+        s.bnorm[i] = s.bnorm[q];
+        s.est[i] = s.est[q];
+        s.its[i] = s.its[q];
+        s.done[i] = s.done[q];
+        s.act[i] = s.act[q];
+        s.jr[i] = s.jr[q];
+        for (int t = 0; t <= m; ++t) {
+            s.sv[i * (m + 1) + t] = s.sv[q * (m + 1) + t];
+            s.g[i * (m + 1) + t] = s.g[q * (m + 1) + t];
+        }
+    }
+}
+
 // End of a cycle: y = R^{-1} g over the jr[r] columns built (back
 // substitution on the rotated Hessenberg matrix).  One thread per RHS.
 __global__ void __launch_bounds__(64)

@@ -221,10 +221,13 @@ struct eh_ctx {
     std::vector<TimerRec> timer_recs;
     std::vector<hipEvent_t> event_pool;
     // captured Arnoldi steps: one graph per step j, valid for graph_nrhs
-    // right-hand sides; used only while no kernel class is being timed
+    // right-hand sides in a solve of graph_stride (the layout stride of the
+    // status records and small arrays); used only while no kernel class is
+    // being timed
     struct GraphEntry { hipGraphExec_t exec = nullptr; hipGraph_t graph = nullptr; };
     std::vector<GraphEntry> graphs;
     int graph_nrhs = -1;
+    int graph_stride = -1;
     bool capturing = false;
     hipStream_t solve_stream = nullptr;
     hipEvent_t order_event = nullptr;      // orders the solve stream after the user's
@@ -278,6 +281,7 @@ void drop_graphs(eh_ctx* c) {
     }
     c->graphs.clear();
     c->graph_nrhs = -1;
+    c->graph_stride = -1;
 }
 
 // Records a start event before and a stop event after the launches in its
@@ -1801,53 +1805,133 @@ void gs_pass(eh_ctx* c, int64_t n, int m, int nrhs, const c128* V, const c128* w
 // right-hand sides only: scale 0, no column counted).  A cycle start
 // computes r = b - H x in FP64, so the last start gives the true residual.
 //
-// The problem enters through three callbacks, each enqueueing on c->s:
-//   op_x(x, W)        W = X x for an FP64 vector (cycle starts)
-//   op_z(z_j, W)      W = X z_j for a preconditioned vector (multigrid precision)
-//   prec(v, sv, z_j)  z_j = M (sv[q * (m+1)] v) per right-hand side q
+// The problem enters through four callbacks, each enqueueing on c->s for
+// the nb right-hand sides currently in the batch:
+//   op_x(x, W, nb)            W = X x for an FP64 vector (cycle starts)
+//   op_z(z_j, W, nb)          W = X z_j for a preconditioned vector (multigrid precision)
+//   prec(v, sv, z_j, nb)      z_j = M (sv[q * (m+1)] v) per right-hand side q
+//   op_res(x, b, r, nrm, nb)  r = b - X x and nrm = |r|^2 in one pass, or false
+//                             where the problem does not provide it
 // with vectors of length n, right-hand side q at offset q * n.  Graph
 // capture is used only for the full system (`graphs`).
+//
+// With drop_converged, a cycle start whose true residuals show some right-
+// hand sides finished (and some not) moves the unfinished ones to the first
+// slots of the batch -- their x and b into buffers of this solve, their
+// cycle-start residual within stored column 0, their Arnoldi state on the
+// device -- and later launches cover only them.  A dropped right-hand side's
+// x goes back to its place in the caller's x.  Every kernel's arithmetic per
+// right-hand side does not depend on the batch around it, so the results
+// and the counts are those of the full batch.
 template <class T, class OpX, class OpZ, class Prec, class OpRes>
 eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool graphs, const c128* b, c128* x,
                       int nrhs, double tol, int maxit, eh_info* info, OpRes op_res) {
     const int m = c->o.restart;
-    const int64_t vstep = (int64_t)nrhs * n;    // distance between basis vectors
+    int nb = nrhs;                               // right-hand sides in the batch
+    int64_t vstep = (int64_t)nb * n;             // distance between basis vectors
     cplx<T>* Z = (cplx<T>*)c->Z;
     ArnState S = c->arn;
-    S.nrhs = nrhs;
+    S.nrhs = nb;
     ArnStatus* hs = c->arn_host;
     ArnStatus* ds = c->arn_dev;
     c128* d1 = c->dsmall;
     c128* d2 = c->dsmall + (size_t)2 * nrhs * (m + 2);
     c128* d3 = c->dsmall + (size_t)4 * nrhs * (m + 2);
-    const unsigned rgrid = (unsigned)((nrhs + 63) / 64);
+    unsigned rgrid = (unsigned)((nb + 63) / 64);
     // predicted estimate below this multiple of tol: wait for the step
     constexpr double kNear = 3.0;
     HIPCHK(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(c128), c->s));
+    // the batch: slot q holds right-hand side orig[q] of the call; its b and
+    // x live in the caller's arrays until the first drop, then in cbuf
+    std::vector<int> orig(nrhs);
+    for (int r = 0; r < nrhs; ++r) orig[r] = r;
+    std::vector<ArnStatus> fin_all(nrhs);
+    const c128* bw = b;
+    c128* xw = x;
+    struct Scratch {
+        eh_ctx* c;
+        c128* buf = nullptr;
+        int* map = nullptr;
+        ~Scratch() {
+            if (buf || map) (void)hipStreamSynchronize(c->s);
+            c->release(buf);
+            c->release(map);
+        }
+    } scr{c};
     int total = 0;
     bool first = true;
     auto status = [&](int slot) { return hs + (size_t)slot * nrhs; };
     auto check_bad = [&](const ArnStatus* st) {
-        for (int r = 0; r < nrhs; ++r)
+        for (int r = 0; r < nb; ++r)
             if (st[r].bad) throw StateError{"non-finite value in the Arnoldi process"};
     };
     auto any_active = [&](const ArnStatus* st) {
-        for (int r = 0; r < nrhs; ++r)
+        for (int r = 0; r < nb; ++r)
             if (st[r].active) return true;
         return false;
+    };
+    auto copy_vec = [&](c128* dst, const c128* src) {
+        HIPCHK(hipMemcpyAsync(dst, src, (size_t)n * sizeof(c128), hipMemcpyDeviceToDevice, c->s));
+    };
+    // Keep the slots listed in keep (increasing), drop the rest.  Called at a
+    // cycle start, after k_arn_start and the host's read of its records.
+    auto drop = [&](const std::vector<int>& keep) {
+        const int k = (int)keep.size();
+        ArnStatus* st = status(m);
+        std::vector<char> kept(nb, 0);
+        for (int q : keep) kept[q] = 1;
+        for (int q = 0; q < nb; ++q)
+            if (!kept[q]) fin_all[orig[q]] = st[q];
+        if (xw == x) {
+            // first drop: the dropped x are already in place; gather the rest
+            scr.buf = c->alloc<c128>((size_t)2 * k * n);
+            scr.map = c->alloc<int>((size_t)nrhs);
+            c128* nx = scr.buf;
+            c128* nbv = scr.buf + (size_t)k * n;
+            for (int i = 0; i < k; ++i) {
+                copy_vec(nx + (size_t)i * n, xw + (size_t)keep[i] * n);
+                copy_vec(nbv + (size_t)i * n, bw + (size_t)keep[i] * n);
+            }
+            xw = nx;
+            bw = nbv;
+        } else {
+            for (int q = 0; q < nb; ++q)
+                if (!kept[q]) copy_vec(x + (size_t)orig[q] * n, xw + (size_t)q * n);
+            for (int i = 0; i < k; ++i)
+                if (keep[i] != i) {
+                    copy_vec(xw + (size_t)i * n, xw + (size_t)keep[i] * n);
+                    copy_vec((c128*)bw + (size_t)i * n, bw + (size_t)keep[i] * n);
+                }
+        }
+        // stored column 0 holds the cycle-start residuals (slot q at q * n)
+        for (int i = 0; i < k; ++i)
+            if (keep[i] != i) copy_vec(c->V + (size_t)i * n, c->V + (size_t)keep[i] * n);
+        HIPCHK(hipMemcpyAsync(scr.map, keep.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice, c->s));
+        hipLaunchKernelGGL(k_arn_compact, dim3(1), dim3(64), 0, c->s, S, (const int*)scr.map, k);
+        HIPCHK(hipGetLastError());
+        // keep.data() must outlive the copy
+        HIPCHK(hipStreamSynchronize(c->s));
+        for (int i = 0; i < k; ++i) {
+            st[i] = st[keep[i]];
+            orig[i] = orig[keep[i]];
+        }
+        nb = k;
+        S.nrhs = nb;
+        vstep = (int64_t)nb * n;
+        rgrid = (unsigned)((nb + 63) / 64);
     };
     for (;;) {
         // r = b - H x into stored column 0; its norm starts the cycle
         if (first) {
-            HIPCHK(hipMemcpyAsync(c->V, b, (size_t)vstep * sizeof(c128), hipMemcpyDeviceToDevice, c->s));
-            gs_pass<3>(c, n, 1, nrhs, nullptr, c->V, nullptr, d3);
-        } else if (!op_res(x, c->V, d3)) {
+            HIPCHK(hipMemcpyAsync(c->V, bw, (size_t)vstep * sizeof(c128), hipMemcpyDeviceToDevice, c->s));
+            gs_pass<3>(c, n, 1, nb, nullptr, c->V, nullptr, d3);
+        } else if (!op_res(xw, bw, c->V, d3, nb)) {
             // (op_res: r and |r|^2 from the operator launch itself, where the
             // problem provides it)
-            op_x(x, c->W);
-            hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, b, c->W, c->V);
+            op_x(xw, c->W, nb);
+            hipLaunchKernelGGL(k_sub, dim3(lin_grid(vstep, 256, 4096)), dim3(256), 0, c->s, vstep, bw, c->W, c->V);
             HIPCHK(hipGetLastError());
-            gs_pass<3>(c, n, 1, nrhs, nullptr, c->V, nullptr, d3);
+            gs_pass<3>(c, n, 1, nb, nullptr, c->V, nullptr, d3);
         }
         hipLaunchKernelGGL(k_arn_start, dim3(rgrid), dim3(64), 0, c->s, S, (const c128*)d3, first ? 1 : 0, tol,
                            ds + (size_t)m * nrhs);
@@ -1856,26 +1940,33 @@ eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool 
         HIPCHK(hipStreamSynchronize(c->s));
         check_bad(status(m));
         if (!any_active(status(m)) || total >= maxit) break;
+        if (c->o.drop_converged) {
+            std::vector<int> keep;
+            for (int q = 0; q < nb; ++q)
+                if (status(m)[q].active) keep.push_back(q);
+            if ((int)keep.size() < nb) drop(keep);
+        }
         int steps = 0;
         for (int j = 0; j < m && total < maxit; ++j) {
             c128* Vj = c->V + (int64_t)j * vstep;
             cplx<T>* Zj = Z + (int64_t)j * vstep;
             auto body = [&]() {
-                prec(Vj, S.sv + j, Zj);
-                op_z(Zj, c->W);
-                gs_pass<4>(c, n, j + 1, nrhs, c->V, c->W, nullptr, d1);
-                hipLaunchKernelGGL(k_arn_coef, dim3(nrhs), dim3(64), 0, c->s, S, j, (const c128*)d1, d2);
+                prec(Vj, S.sv + j, Zj, nb);
+                op_z(Zj, c->W, nb);
+                gs_pass<4>(c, n, j + 1, nb, c->V, c->W, nullptr, d1);
+                hipLaunchKernelGGL(k_arn_coef, dim3(nb), dim3(64), 0, c->s, S, j, (const c128*)d1, d2);
                 HIPCHK(hipGetLastError());
-                gs_pass<2>(c, n, j + 1, nrhs, c->V, c->W, d2, d3, Vj + vstep);
+                gs_pass<2>(c, n, j + 1, nb, c->V, c->W, d2, d3, Vj + vstep);
                 hipLaunchKernelGGL(k_arn_givens, dim3(rgrid), dim3(64), 0, c->s, S, j, (const c128*)d3,
                                    ds + (size_t)j * nrhs);
                 HIPCHK(hipGetLastError());
             };
             if (graphs && c->timer_mask == 0) {
-                if (c->graph_nrhs != nrhs || (int)c->graphs.size() != m) {
+                if (c->graph_nrhs != nb || c->graph_stride != nrhs || (int)c->graphs.size() != m) {
                     drop_graphs(c);
                     c->graphs.resize(m);
-                    c->graph_nrhs = nrhs;
+                    c->graph_nrhs = nb;
+                    c->graph_stride = nrhs;
                 }
                 eh_ctx::GraphEntry& g = c->graphs[j];
                 if (!g.exec) {
@@ -1910,7 +2001,7 @@ eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool 
             if (!any_active(known)) break;
             const ArnStatus* before = j >= 2 ? status(j - 2) : (j == 1 ? status(m) : nullptr);
             bool near = true;
-            for (int r = 0; r < nrhs && near; ++r) {
+            for (int r = 0; r < nb && near; ++r) {
                 if (!known[r].active) continue;
                 double ratio = 1.0;
                 if (before && before[r].est > 0.0) ratio = std::min(1.0, known[r].est / before[r].est);
@@ -1926,23 +2017,27 @@ eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool 
         hipLaunchKernelGGL(k_arn_solve, dim3(rgrid), dim3(64), 0, c->s, S);
         HIPCHK(hipGetLastError());
         {
-            Timed tm(c, KC_KRYLOV, (double)nrhs * n * (2 * sizeof(c128) + steps * sizeof(cplx<T>)));
-            hipLaunchKernelGGL((k_xupdate<T>), dim3(lin_grid(n, 256, 2048), nrhs), dim3(256), 0, c->s, n,
-                               (const int*)S.jr, m, nrhs, (const cplx<T>*)Z, (const c128*)S.y, x);
+            Timed tm(c, KC_KRYLOV, (double)nb * n * (2 * sizeof(c128) + steps * sizeof(cplx<T>)));
+            hipLaunchKernelGGL((k_xupdate<T>), dim3(lin_grid(n, 256, 2048), nb), dim3(256), 0, c->s, n,
+                               (const int*)S.jr, m, nb, (const cplx<T>*)Z, (const c128*)S.y, xw);
             HIPCHK(hipGetLastError());
         }
     }
     // the last cycle start computed the true FP64 residual of x
     const ArnStatus* fin = status(m);
+    for (int q = 0; q < nb; ++q) {
+        fin_all[orig[q]] = fin[q];
+        if (xw != x) copy_vec(x + (size_t)orig[q] * n, xw + (size_t)q * n);
+    }
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
-        const int conv = fin[r].rel < tol;
+        const int conv = fin_all[r].rel < tol;
         all = all && conv;
         if (info) {
-            info[r].iters = fin[r].its;
+            info[r].iters = fin_all[r].its;
             info[r].converged = conv;
-            info[r].relres_true = fin[r].rel;
-            info[r].relres_est = fin[r].est;
+            info[r].relres_true = fin_all[r].rel;
+            info[r].relres_est = fin_all[r].est;
         }
     }
     return all ? EH_OK : EH_NOT_CONVERGED;
@@ -1956,13 +2051,15 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
     maybe_autotune<T>(c, nrhs);
     const int64_t n = c->ndof;
     const int m = c->o.restart;
-    auto op_x = [&](const c128* xx, c128* w) { apply_H<double>(c, xx, n, w, n, nrhs); };
-    auto op_z = [&](const cplx<T>* z, c128* w) { apply_H<T>(c, z, n, w, n, nrhs); };
-    auto op_res = [&](const c128* xx, c128* r, c128* nrm) {
-        residual_H(c, xx, b, r, nrhs, nrm);
+    auto op_x = [&](const c128* xx, c128* w, int nb) { apply_H<double>(c, xx, n, w, n, nb); };
+    auto op_z = [&](const cplx<T>* z, c128* w, int nb) { apply_H<T>(c, z, n, w, n, nb); };
+    auto op_res = [&](const c128* xx, const c128* bb, c128* r, c128* nrm, int nb) {
+        residual_H(c, xx, bb, r, nb, nrm);
         return true;
     };
-    auto prec = [&](const c128* v, const double* sv, cplx<T>* z) { apply_M<T>(c, v, n, z, n, nrhs, sv, m + 1); };
+    auto prec = [&](const c128* v, const double* sv, cplx<T>* z, int nb) {
+        apply_M<T>(c, v, n, z, n, nb, sv, m + 1);
+    };
     return fgmres_core<T>(c, n, op_x, op_z, prec, c->o.graphs != 0, b, x, nrhs, tol, maxit, info, op_res);
 }
 
@@ -1982,34 +2079,34 @@ eh_status block_solve_impl(eh_ctx* c, int block, const c128* f, c128* x, int nrh
     const int64_t n = L.d.np();
     const int m = c->o.restart;
     const int kinds[1] = {block};
-    auto apply_T = [&](const cplx<T>* u, int64_t vu, c128* w) {
+    auto apply_T = [&](const cplx<T>* u, int64_t vu, c128* w, int nb) {
         GArgs<T> a = gbase<T>(c, kinds, 1, 0, false);
         a.u[0] = u;
         a.vu[0] = vu;
         a.out[0] = (cplx<T>*)L.t;
         a.vo[0] = n;
-        gsweep<T>(c, a, 0, 3, nrhs);
-        hipLaunchKernelGGL((k_cast<double, T>), dim3(lin_grid(n * nrhs, 256, 8192)), dim3(256), 0, c->s,
-                           n * nrhs, (const cplx<T>*)L.t, w);
+        gsweep<T>(c, a, 0, 3, nb);
+        hipLaunchKernelGGL((k_cast<double, T>), dim3(lin_grid(n * nb, 256, 8192)), dim3(256), 0, c->s,
+                           n * nb, (const cplx<T>*)L.t, w);
         HIPCHK(hipGetLastError());
     };
-    auto op_x = [&](const c128* xx, c128* w) {
-        hipLaunchKernelGGL((k_cast_scaled<T>), dim3(lin_grid(n, 256, 4096), nrhs), dim3(256), 0, c->s, n, xx, n,
+    auto op_x = [&](const c128* xx, c128* w, int nb) {
+        hipLaunchKernelGGL((k_cast_scaled<T>), dim3(lin_grid(n, 256, 4096), nb), dim3(256), 0, c->s, n, xx, n,
                            (const double*)nullptr, (int64_t)0, (cplx<T>*)L.u, n);
         HIPCHK(hipGetLastError());
-        apply_T((const cplx<T>*)L.u, n, w);
+        apply_T((const cplx<T>*)L.u, n, w, nb);
     };
-    auto op_z = [&](const cplx<T>* z, c128* w) { apply_T(z, n, w); };
-    auto prec = [&](const c128* v, const double* sv, cplx<T>* z) {
-        hipLaunchKernelGGL((k_cast_scaled<T>), dim3(lin_grid(n, 256, 4096), nrhs), dim3(256), 0, c->s, n, v, n,
+    auto op_z = [&](const cplx<T>* z, c128* w, int nb) { apply_T(z, n, w, nb); };
+    auto prec = [&](const c128* v, const double* sv, cplx<T>* z, int nb) {
+        hipLaunchKernelGGL((k_cast_scaled<T>), dim3(lin_grid(n, 256, 4096), nb), dim3(256), 0, c->s, n, v, n,
                            sv, (int64_t)(m + 1), (cplx<T>*)L.f, n);
         HIPCHK(hipGetLastError());
         const void* fa[1] = {L.f};
         const int64_t vf[1] = {n};
         void* out[1] = {z};
-        gcycle<T>(c, kinds, 1, 0, fa, vf, out, vf, false, nrhs);
+        gcycle<T>(c, kinds, 1, 0, fa, vf, out, vf, false, nb);
     };
-    auto no_res = [](const c128*, c128*, c128*) { return false; };
+    auto no_res = [](const c128*, const c128*, c128*, c128*, int) { return false; };
     return fgmres_core<T>(c, n, op_x, op_z, prec, false, f, x, nrhs, tol, maxit, info, no_res);
 }
 
@@ -2162,6 +2259,7 @@ void eh_default_opts(eh_opts* o) {
     o->fused = 1;
     o->ap_variant = 0;
     o->coarse_solver = 0;
+    o->drop_converged = 1;
 }
 
 const char* eh_last_error(const eh_ctx* c) {
@@ -2198,6 +2296,9 @@ eh_status eh_create(eh_ctx** out, int dim, const int64_t* n, const double* h, co
     if (o.graphs != 0 && o.graphs != 1) { g_create_error = "graphs must be 0 or 1"; return EH_ERR_ARG; }
     if (o.autotune != 0 && o.autotune != 1) { g_create_error = "autotune must be 0 or 1"; return EH_ERR_ARG; }
     if (o.fused != 0 && o.fused != 1) { g_create_error = "fused must be 0 or 1"; return EH_ERR_ARG; }
+    if (o.drop_converged != 0 && o.drop_converged != 1) {
+        g_create_error = "drop_converged must be 0 or 1"; return EH_ERR_ARG;
+    }
     if (o.ap_variant != 0 && o.ap_variant != 1) { g_create_error = "ap_variant must be 0 or 1"; return EH_ERR_ARG; }
     if (o.coarse_solver < 0 || o.coarse_solver > 2) {
         g_create_error = "coarse_solver must be 0 (auto), 1 (dense) or 2 (block-tridiagonal)"; return EH_ERR_ARG;

@@ -49,7 +49,7 @@ class ElasticHelmholtz:
                  nu=(1, 2), damping=(0.8, 0.8, 0.3), alpha=0.1,
                  mg_precision=32, restart=20, abc_width=20, abc_sides=None,
                  gamma0=0.01 * math.pi, intergrid="full", graphs=True, autotune=True, fused=True,
-                 ap_variant="A_p", coarse_solver="auto",
+                 ap_variant="A_p", coarse_solver="auto", drop_converged=True,
                  stream=None):
         L = N.lib()
         self._lib = L
@@ -77,6 +77,7 @@ class ElasticHelmholtz:
         opts.ap_variant = {"A_p": 0, "tilde": 1}[ap_variant] if isinstance(ap_variant, str) else int(ap_variant)
         opts.coarse_solver = ({"auto": 0, "dense": 1, "bt": 2}[coarse_solver] if isinstance(coarse_solver, str)
                               else int(coarse_solver))
+        opts.drop_converged = 1 if drop_converged else 0
         self.opts = opts
         arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel()) for a in (vp, vs, rho)]
         ncell = int(np.prod(self.n))

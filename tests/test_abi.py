@@ -36,7 +36,7 @@ def test_default_opts():
     assert o.mg_precision == 32 and o.restart == 20 and o.abc_width == 20
     assert o.gamma0 == pytest.approx(0.01 * math.pi)
     assert (o.intergrid, o.graphs, o.autotune, o.fused, o.ap_variant) == (0, 1, 1, 1, 0)
-    assert o.coarse_solver == 0
+    assert o.coarse_solver == 0 and o.drop_converged == 1
 
 
 def _create(n, vp, vs, rho, omega=1.0, levels=2, dim=None, **kw):
@@ -59,7 +59,7 @@ def _create(n, vp, vs, rho, omega=1.0, levels=2, dim=None, **kw):
 
 @pytest.mark.parametrize("case", ["vs>=vp", "rho<=0", "nan", "divisibility", "dim", "omega",
                                   "precision", "restart", "levels", "fused", "ap_variant",
-                                  "coarse_solver", "dense_too_large"])
+                                  "coarse_solver", "dense_too_large", "drop_converged"])
 def test_invalid_arguments_are_rejected_before_device_work(case):
     n = (8, 8)
     vp, vs, rho = np.full(64, 2.0), np.full(64, 1.0), np.full(64, 1.0)
@@ -89,6 +89,8 @@ def test_invalid_arguments_are_rejected_before_device_work(case):
         kw["ap_variant"] = 3
     elif case == "coarse_solver":
         kw["coarse_solver"] = 3
+    elif case == "drop_converged":
+        kw["drop_converged"] = 2
     elif case == "dense_too_large":
         n = (128, 128)                   # one level: 16 512 points > 6000
         vp, vs, rho = np.full(128 * 128, 2.0), np.full(128 * 128, 1.0), np.full(128 * 128, 1.0)
