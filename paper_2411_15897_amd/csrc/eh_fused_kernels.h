@@ -111,17 +111,25 @@ __device__ __forceinline__ cplx<T> fuse_sc(const GArgs<T>& a, int slot, int64_t 
 // not depend on which tile, or which phase of a tile, computes it.  The up
 // leg keeps its own tile point's operator for both sweeps and every
 // right-hand side.
+//
+// On the fine level the diagonal drops out of a damped Jacobi update:
+// u + w D^-1 (f - D u + s) = (1 - w) u + w D^-1 (f + s), s = sum_nb c_nb u_nb,
+// and, for the residual of the first sweep from zero (u = w D^-1 f at the
+// point), f - X u = (1 - w) f + s.  Both are evaluated in these forms (no
+// multiplication by D), with the neighbour sum as fused multiply-adds in a
+// fixed order.
 template <class T, bool FINE, int KIND, int WX, int WY, bool HALF = false>
 struct PointOp {
     static constexpr int NST = (2 * WX + 1) * (2 * WY + 1);
     cplx<T> cf[FINE ? 1 : NST];
     FineCoef<T, KIND, 2> fc;
-    cplx<T> D, sc;
+    cplx<T> sc;
+    T omw;   // fine level: 1 - w
     __device__ __forceinline__ void load(const GArgs<T>& a, int slot, const Dims& d, int gx, int gy, int64_t p) {
         sc = fuse_sc<T, FINE>(a, slot, p);
         if (FINE) {
             fc.load(d, gx, gy, 0, p, a.w[slot][0], a.w[slot][1], a.w[slot][2], a.ih[0], a.ih[1], a.ih[2]);
-            D = a.D[slot][p];
+            omw = T(1) - a.damp;
         } else {
             const int64_t np = d.np();
 #pragma unroll
@@ -134,14 +142,23 @@ struct PointOp {
             }
         }
     }
-    // X u with u from an LDS array of row pitch SX at local index l
+    // fine level: acc + sum_nb c_nb u_nb (real couplings)
+    template <int SX>
+    __device__ __forceinline__ cplx<T> nbsum(const cplx<T>* S, int l, cplx<T> acc) const {
+        const cplx<T> e = S[l + 1], w = S[l - 1], n = S[l + SX], s = S[l - SX];
+        acc.re = fmat(fc.cp[0], e.re, acc.re);
+        acc.im = fmat(fc.cp[0], e.im, acc.im);
+        acc.re = fmat(fc.cm[0], w.re, acc.re);
+        acc.im = fmat(fc.cm[0], w.im, acc.im);
+        acc.re = fmat(fc.cp[1], n.re, acc.re);
+        acc.im = fmat(fc.cp[1], n.im, acc.im);
+        acc.re = fmat(fc.cm[1], s.re, acc.re);
+        acc.im = fmat(fc.cm[1], s.im, acc.im);
+        return acc;
+    }
+    // stored stencils: X u with u from an LDS array of row pitch SX at local index l
     template <int SX>
     __device__ __forceinline__ cplx<T> apply(const cplx<T>* S, int l) const {
-        if (FINE) {
-            const cplx<T> offs =
-                fc.cp[0] * S[l + 1] + fc.cm[0] * S[l - 1] + fc.cp[1] * S[l + SX] + fc.cm[1] * S[l - SX];
-            return D * S[l] - offs;
-        }
         cplx<T> xu = czero<T>();
 #pragma unroll
         for (int oy = -WY; oy <= WY; ++oy)
@@ -150,10 +167,18 @@ struct PointOp {
                 xu = cfma(cf[FINE ? 0 : (oy + WY) * (2 * WX + 1) + (ox + WX)], S[l + oy * SX + ox], xu);
         return xu;
     }
+    // f - X u where u is the first sweep from zero (u = w D^-1 f here)
+    template <int SX>
+    __device__ __forceinline__ cplx<T> first_resid(const cplx<T>* S, int l, cplx<T> fp) const {
+        if (FINE) return nbsum<SX>(S, l, mk<T>(omw * fp.re, omw * fp.im));
+        return fp - apply<SX>(S, l);
+    }
     // one damped Jacobi update u + w D^-1 (f - X u) at local index l
     template <int SX>
     __device__ __forceinline__ cplx<T> sweep(const cplx<T>* S, int l, cplx<T> fp) const {
-        return cfma(sc, fp - apply<SX>(S, l), S[l]);
+        const cplx<T> u = S[l];
+        if (FINE) return cfma(sc, nbsum<SX>(S, l, fp), mk<T>(omw * u.re, omw * u.im));
+        return cfma(sc, fp - apply<SX>(S, l), u);
     }
 };
 
@@ -266,13 +291,14 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
         }
         if (ONE_R) {
             if ((int)threadIdx.x < RX * RY)
-                RR[threadIdx.x] = rin ? fr - rop.template apply<UX>(U, (my_ry + WY) * UX + (my_rx + WX)) : czero<T>();
+                RR[threadIdx.x] =
+                    rin ? rop.template first_resid<UX>(U, (my_ry + WY) * UX + (my_rx + WX), fr) : czero<T>();
         } else if (HOLD) {
 #pragma unroll
             for (int it = 0; it < NR; ++it) {
                 const int q = threadIdx.x + it * NT;
                 if (q >= RX * RY) break;
-                RR[q] = hp[it] >= 0 ? fhold[it] - hop[it].template apply<UX>(U, hl[it]) : czero<T>();
+                RR[q] = hp[it] >= 0 ? hop[it].template first_resid<UX>(U, hl[it], fhold[it]) : czero<T>();
             }
         } else {
 #pragma unroll 1
@@ -287,7 +313,7 @@ __device__ __forceinline__ void down_body(const GArgs<T>& a, int slot, cplx<T>* 
                     const int l = (ry + WY) * UX + (rx + WX);
                     PointOp<T, FINE, KIND, WX, WY, !FINE && NM != 0 && !MIXED> op;
                     op.load(a, slot, d, gx, gy, p);
-                    v = f[p] - op.template apply<UX>(U, l);
+                    v = op.template first_resid<UX>(U, l, f[p]);
                 }
                 RR[q] = v;
             }
