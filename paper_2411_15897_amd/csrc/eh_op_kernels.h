@@ -167,11 +167,28 @@ k_op(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int nrhs, 
 // side's into registers while this one is computed from LDS: one barrier
 // per right-hand side.  Values outside a field are zero (the zero ghosts of
 // the operator).  Same arithmetic per point as k_op.
+//
+// DOTS: the launch also does the first Gram-Schmidt pass of the Arnoldi
+// step on the vector it writes, w = H z: for the stored basis columns
+// t < J it forms, per right-hand side and workgroup, the partial sums
+// conj(V_t) . w and conj(V_t) . V_{J-1} over the workgroup's degrees of
+// freedom (each thread's faces and cell, then the wavefront butterfly, then
+// the four wavefronts in a fixed order), so w need not be read back for
+// them.  Partials [r][2J][workgroup]; k_reduce_partials adds them in a fixed
+// order.
+struct DotArgs {
+    const c128* V;       // basis: column t of RHS r at V + t * vstep + r * (the output stride)
+    int64_t vstep;
+    int J;               // columns 0 .. J-1 (J <= KRY_MAXM)
+    c128* partial;
+};
+
 constexpr int OTX = 64, OTY = 4;
-template <class Tin, bool RES>
+constexpr int OP_MAXJ = 32;
+template <class Tin, bool RES, bool DOTS = false>
 __global__ void __launch_bounds__(256)
 k_op2_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int nrhs, int64_t vs_in, int64_t vs_out,
-          ResArgs ra, int rch) {
+          ResArgs ra, int rch, DotArgs da = DotArgs{}) {
     constexpr int UW = OTX + 2, UH = OTY + 2;        // u_a box: [x0-1, x0+OTX] x [y0-1, y0+OTY]
     constexpr int PW = OTX + 1, PH = OTY + 1;        // p box:   [x0-1, x0+OTX-1] x [y0-1, y0+OTY-1]
     constexpr int NU = UW * UH, NP = PW * PH, NS = 2 * NU + NP;
@@ -249,6 +266,7 @@ k_op2_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int n
         double rr = 0.0;
         const c128 pcv = ccast<double>(S[lp]);
         c128 div = mk(0.0, 0.0);
+        c128 yk[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};   // w at the faces and the cell
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             if (!face[a]) continue;
@@ -268,6 +286,7 @@ k_op2_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int n
                 rr += yv.re * yv.re + yv.im * yv.im;
             }
             y[r * vs_out + o.off[a] + fp[a]] = yv;
+            yk[a] = yv;
         }
         if (cell) {
             c128 yv = mk(-div.re - Cp * pcv.re, -div.im - Cp * pcv.im);
@@ -276,8 +295,55 @@ k_op2_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int n
                 rr += yv.re * yv.re + yv.im * yv.im;
             }
             y[r * vs_out + o.off[2] + pc] = yv;
+            yk[2] = yv;
         }
         if (RES) res_partial(ra, r, 0, rr);
+        if (DOTS) {
+            __shared__ double red[4][4 * OP_MAXJ];
+            const int J = da.J;
+            const int lane = tid & 63, wave = tid >> 6;
+            const bool has[3] = {face[0], face[1], cell};
+            const int64_t at[3] = {o.off[0] + fp[0], o.off[1] + fp[1], o.off[2] + pc};
+            const c128* Vl = da.V + (int64_t)(J - 1) * da.vstep + r * vs_out;
+            c128 vl[3];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) vl[e] = has[e] ? Vl[at[e]] : mk(0.0, 0.0);
+            for (int t = 0; t < J; ++t) {
+                const c128* Vt = da.V + (int64_t)t * da.vstep + r * vs_out;
+                double ar = 0.0, ai = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const c128 v = t == J - 1 ? vl[e] : (has[e] ? Vt[at[e]] : mk(0.0, 0.0));
+                    ar += v.re * yk[e].re + v.im * yk[e].im;
+                    ai += v.re * yk[e].im - v.im * yk[e].re;
+                    gr += v.re * vl[e].re + v.im * vl[e].im;
+                    gi += v.re * vl[e].im - v.im * vl[e].re;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    ar += __shfl_xor(ar, off, 64);
+                    ai += __shfl_xor(ai, off, 64);
+                    gr += __shfl_xor(gr, off, 64);
+                    gi += __shfl_xor(gi, off, 64);
+                }
+                if (lane == 0) {
+                    red[wave][4 * t] = ar;
+                    red[wave][4 * t + 1] = ai;
+                    red[wave][4 * t + 2] = gr;
+                    red[wave][4 * t + 3] = gi;
+                }
+            }
+            __syncthreads();
+            if (tid < 2 * J) {
+                const int t = tid % J, g = tid / J;   // g = 0: conj(V_t) w, 1: conj(V_t) V_{J-1}
+                const int q = 4 * t + 2 * g;
+                const double sr = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+                const double si = (red[0][q + 1] + red[1][q + 1]) + (red[2][q + 1] + red[3][q + 1]);
+                const int64_t nt = (int64_t)gridDim.x * gridDim.y;
+                const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+                da.partial[((int64_t)r * 2 * J + g * J + t) * nt + blk] = mk(sr, si);
+            }
+            __syncthreads();   // red is reused by the next right-hand side
+        }
     }
 }
 

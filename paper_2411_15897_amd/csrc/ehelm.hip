@@ -1606,6 +1606,43 @@ void apply_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs
     launch_H<Tin, false>(c, x, vx, y, vy, nrhs, ResArgs{});
 }
 
+// w = H z for nrhs vectors in the multigrid precision and, from the same
+// launch (2D), the first Gram-Schmidt pass of the Arnoldi step: d1 row r =
+// [conj(V_t) . w for t < J, conj(V_t) . V_{J-1} for t < J] with basis
+// column t of RHS r at V + t * vstep + r * ndof.  Returns false in 3D,
+// where the caller runs the pass over w itself.
+template <class Tin>
+bool apply_H_dots(eh_ctx* c, const void* z, c128* w, int nrhs, const c128* V, int64_t vstep, int J, c128* d1) {
+    if (c->dim != 2 || J > OP_MAXJ) return false;
+    double coefb = 8.0 * c->ncell;
+    for (int k = 0; k < c->dim; ++k) coefb += (double)c->fsize[k] * (8.0 * c->dim + 16.0);
+    Timed tm(c, KC_OPERATOR,
+             coefb + (double)nrhs * c->ndof * (sizeof(cplx<Tin>) + sizeof(c128) + J * sizeof(c128)));
+    OpArgs o{};
+    o.dc = c->dcell;
+    for (int a = 0; a < 3; ++a) {
+        o.ih[a] = 1.0 / c->h[a];
+        if (a < c->dim) {
+            o.df[a] = c->dface[a];
+            for (int b = 0; b < 3; ++b) o.w[a][b] = c->k1w[a][b];
+            o.D[a] = c->k1D[a];
+        }
+    }
+    for (int a = 0; a < 4; ++a) o.off[a] = c->off[a];
+    o.C = c->C;
+    const dim3 g = op_grid(c);
+    const int rch = rhs_chunk((int)(g.x * g.y * g.z), 1, nrhs);
+    const dim3 gc(g.x, g.y, g.z * (unsigned)((std::max(nrhs, 1) + rch - 1) / rch));
+    DotArgs da{V, vstep, J, c->partial};
+    hipLaunchKernelGGL((k_op2_lds<Tin, false, true>), gc, dim3(256), 0, c->s, o, (const cplx<Tin>*)z, w, nrhs,
+                       c->ndof, c->ndof, ResArgs{}, rch, da);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_partials, dim3(2 * J, nrhs), dim3(256), 0, c->s, (int)(g.x * g.y), 2 * J, nrhs,
+                       c->partial, d1);
+    HIPCHK(hipGetLastError());
+    return true;
+}
+
 // r = b - H x for nrhs complex128 vectors of stride ndof, and nrm[q] =
 // |r_q|^2 (the cycle start of FGMRES) from the same launches.
 void residual_H(eh_ctx* c, const c128* x, const c128* b, c128* r, int nrhs, c128* nrm) {
@@ -1731,7 +1768,9 @@ void ensure_krylov(eh_ctx* c, int nrhs, int m) {
     c->Z = c->alloc<char>((size_t)m * nrhs * c->ndof * c->csize());
     c->W = c->alloc<c128>((size_t)nrhs * c->ndof);
     c->kry_nblk = (int)std::max<int64_t>(1, (c->ndof + KRY_E * KRY_THREADS - 1) / (KRY_E * KRY_THREADS));
-    c->partial = c->alloc<c128>((size_t)c->kry_nblk * nrhs * 2 * (m + 1));
+    // Gram-Schmidt partials: the k_gs blocks, or the operator workgroups
+    // where the 2D operator launch does the first pass
+    c->partial = c->alloc<c128>((size_t)std::max(c->kry_nblk, op_blocks(c)) * nrhs * 2 * (m + 1));
     c->res_partial = c->alloc<c128>((size_t)op_blocks(c) * nrhs);
     c->dsmall = c->alloc<c128>((size_t)6 * nrhs * (m + 2));
     // Arnoldi state: one allocation carved into 16-byte aligned arrays
@@ -1809,6 +1848,10 @@ void gs_pass(eh_ctx* c, int64_t n, int m, int nrhs, const c128* V, const c128* w
 // the nb right-hand sides currently in the batch:
 //   op_x(x, W, nb)            W = X x for an FP64 vector (cycle starts)
 //   op_z(z_j, W, nb)          W = X z_j for a preconditioned vector (multigrid precision)
+//   op_zd(z_j, W, nb, V, vstep, J, d1)
+//                             the same and the first Gram-Schmidt pass over
+//                             columns 0..J-1 into d1 from the same launch, or
+//                             false where the problem does not provide it
 //   prec(v, sv, z_j, nb)      z_j = M (sv[q * (m+1)] v) per right-hand side q
 //   op_res(x, b, r, nrm, nb)  r = b - X x and nrm = |r|^2 in one pass, or false
 //                             where the problem does not provide it
@@ -1823,9 +1866,9 @@ void gs_pass(eh_ctx* c, int64_t n, int m, int nrhs, const c128* V, const c128* w
 // x goes back to its place in the caller's x.  Every kernel's arithmetic per
 // right-hand side does not depend on the batch around it, so the results
 // and the counts are those of the full batch.
-template <class T, class OpX, class OpZ, class Prec, class OpRes>
-eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool graphs, const c128* b, c128* x,
-                      int nrhs, double tol, int maxit, eh_info* info, OpRes op_res) {
+template <class T, class OpX, class OpZ, class OpZD, class Prec, class OpRes>
+eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, OpZD op_zd, Prec prec, bool graphs, const c128* b,
+                      c128* x, int nrhs, double tol, int maxit, eh_info* info, OpRes op_res) {
     const int m = c->o.restart;
     int nb = nrhs;                               // right-hand sides in the batch
     int64_t vstep = (int64_t)nb * n;             // distance between basis vectors
@@ -1952,8 +1995,10 @@ eh_status fgmres_core(eh_ctx* c, int64_t n, OpX op_x, OpZ op_z, Prec prec, bool 
             cplx<T>* Zj = Z + (int64_t)j * vstep;
             auto body = [&]() {
                 prec(Vj, S.sv + j, Zj, nb);
-                op_z(Zj, c->W, nb);
-                gs_pass<4>(c, n, j + 1, nb, c->V, c->W, nullptr, d1);
+                if (!op_zd(Zj, c->W, nb, c->V, vstep, j + 1, d1)) {
+                    op_z(Zj, c->W, nb);
+                    gs_pass<4>(c, n, j + 1, nb, c->V, c->W, nullptr, d1);
+                }
                 hipLaunchKernelGGL(k_arn_coef, dim3(nb), dim3(64), 0, c->s, S, j, (const c128*)d1, d2);
                 HIPCHK(hipGetLastError());
                 gs_pass<2>(c, n, j + 1, nb, c->V, c->W, d2, d3, Vj + vstep);
@@ -2060,7 +2105,10 @@ eh_status solve_impl(eh_ctx* c, const c128* b, c128* x, int nrhs, double tol, in
     auto prec = [&](const c128* v, const double* sv, cplx<T>* z, int nb) {
         apply_M<T>(c, v, n, z, n, nb, sv, m + 1);
     };
-    return fgmres_core<T>(c, n, op_x, op_z, prec, c->o.graphs != 0, b, x, nrhs, tol, maxit, info, op_res);
+    auto op_zd = [&](const cplx<T>* z, c128* w, int nb, const c128* V, int64_t vstep, int J, c128* d1) {
+        return apply_H_dots<T>(c, z, w, nb, V, vstep, J, d1);
+    };
+    return fgmres_core<T>(c, n, op_x, op_z, op_zd, prec, c->o.graphs != 0, b, x, nrhs, tol, maxit, info, op_res);
 }
 
 eh_status fail(eh_ctx* c, eh_status st, const std::string& msg);
@@ -2107,7 +2155,8 @@ eh_status block_solve_impl(eh_ctx* c, int block, const c128* f, c128* x, int nrh
         gcycle<T>(c, kinds, 1, 0, fa, vf, out, vf, false, nb);
     };
     auto no_res = [](const c128*, const c128*, c128*, c128*, int) { return false; };
-    return fgmres_core<T>(c, n, op_x, op_z, prec, false, f, x, nrhs, tol, maxit, info, no_res);
+    auto no_zd = [](const cplx<T>*, c128*, int, const c128*, int64_t, int, c128*) { return false; };
+    return fgmres_core<T>(c, n, op_x, op_z, no_zd, prec, false, f, x, nrhs, tol, maxit, info, no_res);
 }
 
 void ensure_zbuf(eh_ctx* c) {
