@@ -147,7 +147,7 @@ CLASS_KERNELS = {
     "coarse_down": (("eh::k_fdown<float, false", "eh::k_fdown<double, false"), None),
     "coarse_up": (("eh::k_fup<float, false", "eh::k_fup<double, false"), None),
     "coarse": (("eh::k_gstencil<",), None),
-    "operator": (("eh::k_op<", "eh::k_op2_lds<"), None),
+    "operator": (("eh::k_op2_lds<", "eh::k_op3_lds<"), None),
     "distribute": (("eh::k_distribute<",), None),
     "couple": (("eh::k_gcouple<",), None),
     "dense": (("eh::k_gdense<", "eh::k_bt_fwd<", "eh::k_bt_back<"), None),

@@ -1,6 +1,7 @@
 // Elastic operator, distributor and coupling kernels (FP64 inputs).
 //
-//  k_op: y = H x (eq. mixed-discretized), every field in one launch.
+//  k_op2_lds / k_op3_lds: y = H x (eq. mixed-discretized), every field in
+//      one launch (2D / 3D).
 //  k_distribute: t = B r_u - A_p r_p (eq. mixed-distributed) with
 //      A_p r = B B^T (mu r) - w^2 rho (1 - i gamma/w) r (eq. Ap), written in
 //      the multigrid precision.  With rs given, the input of RHS r is
@@ -59,114 +60,25 @@ struct OpArgs {
 // y = H x (all fields) in one launch over the grid of (n1+1) x (n2+1) (x
 // (n3+1)) points: the thread at (i, j, k) owns the a-face (i, j, k) of every
 // face grid that has it and the cell (i, j, k) if it exists, keeps their
-// coefficients in registers for the whole batch, and loads each right-hand
+// coefficients in registers for the whole batch, and reads each right-hand
 // side's u_a around its faces once: the same values give the stencil of A_a
 // and the divergence of its cell.  Rows of u_a: A_a u_a + B_a^T p with
 // B_a^T p = (p(c) - p(c - e_a)) / h_a (zero ghost p); rows of p:
 // -sum_a (u_a(c + e_a) - u_a(c)) / h_a - p / (lambda + mu).
 //
-// Launch: blockDim (64, 4), gridDim (x tiles, y tiles, planes x chunks of the
-// batch); workgroup z takes plane z % planes and right-hand sides
-// [c * rch, min(nrhs, c * rch + rch)) with c = z / planes.
-template <class Tin, int DIM, bool RES>
-__global__ void __launch_bounds__(256)
-k_op(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int nrhs, int64_t vs_in, int64_t vs_out,
-     ResArgs ra, int rch) {
-    const int planes = DIM == 3 ? o.dc.g[2] + 1 : 1;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z % planes;
-    const int rlo = (blockIdx.z / planes) * rch, rhi = min(nrhs, rlo + rch);
-    const int n0 = o.dc.g[0], n1 = o.dc.g[1], n2 = DIM == 3 ? o.dc.g[2] : 1;
-    const bool inx = i <= n0 && j <= n1;
-    if (!RES && !inx) return;
-    const int ci[3] = {i, j, k};
-    const int nn[3] = {n0, n1, n2};
-    bool face[3] = {false, false, false};
-    int64_t fp[3] = {0, 0, 0}, fsy[3] = {0, 0, 0}, fsz[3] = {0, 0, 0};
-    FineCoef<double, 0, DIM> cf[DIM];
-    c128 Dp[DIM];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        bool ok = inx;
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) if (b != a && ci[b] >= nn[b]) ok = false;
-        face[a] = ok;
-        const Dims& d = o.df[a];
-        fsy[a] = d.g[0];
-        fsz[a] = (int64_t)d.g[0] * d.g[1];
-        fp[a] = k * fsz[a] + j * fsy[a] + i;
-        Dp[a] = mk(0.0, 0.0);
-        if (ok) {
-            cf[a].load(d, i, j, k, fp[a], o.w[a][0], o.w[a][1], o.w[a][2], 0.0, 0.0, 0.0);
-            Dp[a] = o.D[a][fp[a]];
-        } else {
-#pragma unroll
-            for (int b = 0; b < 3; ++b) { cf[a].cp[b] = 0.0; cf[a].cm[b] = 0.0; }
-        }
-    }
-    const bool cell = inx && i < n0 && j < n1 && k < n2;
-    const int64_t csy = n0, csz = (int64_t)n0 * n1;
-    const int64_t pc = k * csz + j * csy + i;
-    const double Cp = cell ? o.C[pc] : 0.0;
-    const int64_t cst[3] = {1, csy, csz};
-    for (int r = rlo; r < rhi; ++r) {
-        const cplx<Tin>* xr = x + r * vs_in;
-        const cplx<Tin>* pr = xr + o.off[DIM];
-        double rr = 0.0;
-        const c128 pcv = cell ? ccast<double>(pr[pc]) : mk(0.0, 0.0);
-        c128 div = mk(0.0, 0.0);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            if (!face[a]) continue;
-            const Dims& d = o.df[a];
-            const cplx<Tin>* ur = xr + o.off[a];
-            const int64_t p = fp[a];
-            const c128 uc = ccast<double>(ur[p]);
-            // the +e_a neighbour is the other face of this thread's cell
-            c128 up[3], um[3];
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) {
-                const int64_t sb = b == 0 ? 1 : (b == 1 ? fsy[a] : fsz[a]);
-                up[b] = ci[b] + 1 < d.g[b] ? ccast<double>(ur[p + sb]) : mk(0.0, 0.0);
-                um[b] = ci[b] > 0 ? ccast<double>(ur[p - sb]) : mk(0.0, 0.0);
-            }
-            if (cell) div = div + o.ih[a] * (up[a] - uc);
-            c128 s = mk(0.0, 0.0);
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) s = s + cf[a].cp[b] * up[b] + cf[a].cm[b] * um[b];
-            // p at the cells on both sides of the face (zero ghost outside)
-            c128 g = ci[a] < nn[a] ? pcv : mk(0.0, 0.0);
-            if (ci[a] > 0) g = g - ccast<double>(pr[pc - cst[a]]);
-            c128 yv = Dp[a] * uc - s + o.ih[a] * g;
-            c128* yo = y + r * vs_out + o.off[a];
-            if (RES) {
-                yv = ra.b[r * vs_out + o.off[a] + p] - yv;
-                rr += yv.re * yv.re + yv.im * yv.im;
-            }
-            yo[p] = yv;
-        }
-        if (cell) {
-            c128 yv = mk(-div.re - Cp * pcv.re, -div.im - Cp * pcv.im);
-            if (RES) {
-                yv = ra.b[r * vs_out + o.off[DIM] + pc] - yv;
-                rr += yv.re * yv.re + yv.im * yv.im;
-            }
-            y[r * vs_out + o.off[DIM] + pc] = yv;
-        }
-        if (RES) res_partial(ra, r, k, rr);
-    }
-}
+// Launch: blockDim 256 (OTX x OTY points), gridDim (x tiles, y tiles,
+// planes x chunks of the batch); workgroup z takes plane z % planes and
+// right-hand sides [c * rch, min(nrhs, c * rch + rch)) with c = z / planes.
 
-// 2D, several right-hand sides per workgroup: k_op with each right-hand
-// side's inputs staged in LDS.  A workgroup owns OTX x OTY points of the
-// (n1+1) x (n2+1) grid (the same ownership as k_op); per right-hand side it
+// 2D, several right-hand sides per workgroup, each right-hand side's inputs
+// staged in LDS.  A workgroup owns OTX x OTY points of the (n1+1) x (n2+1)
+// grid; per right-hand side it
 // loads the u_1 and u_2 faces of its box plus one point around it and the p
 // cells of its box plus one below and to the left -- every value once,
 // coalesced along x -- into one of two LDS buffers, and the next right-hand
 // side's into registers while this one is computed from LDS: one barrier
 // per right-hand side.  Values outside a field are zero (the zero ghosts of
-// the operator).  Same arithmetic per point as k_op.
+// the operator).
 //
 // DOTS: the launch also does the first Gram-Schmidt pass of the Arnoldi
 // step on the vector it writes, w = H z: for the stored basis columns
@@ -344,6 +256,157 @@ k_op2_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int n
             }
             __syncthreads();   // red is reused by the next right-hand side
         }
+    }
+}
+
+// 3D, several right-hand sides per workgroup, each right-hand side's plane
+// staged in LDS.  A workgroup owns OTX x OTY points of plane k of the
+// (n1+1) x (n2+1) x (n3+1) grid; per right-hand side it stages u_1, u_2, u_3 at plane k over its
+// box plus one point around it and p at plane k over its box plus one
+// below and to the left -- every value once, coalesced along x -- into one
+// of two LDS buffers, and loads the values one plane below and above that
+// the z-stencils, the z-face pressure difference and the divergence need
+// (u_a at k-1 and k+1 of the own faces, p at k-1 of the own cell) straight
+// from memory; the next right-hand side's loads are in flight while this
+// one is computed.  One barrier per right-hand side.
+template <class Tin, bool RES>
+__global__ void __launch_bounds__(256)
+k_op3_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int nrhs, int64_t vs_in, int64_t vs_out,
+          ResArgs ra, int rch) {
+    constexpr int UW = OTX + 2, UH = OTY + 2;
+    constexpr int PW = OTX + 1, PH = OTY + 1;
+    constexpr int NU = UW * UH, NP = PW * PH, NS = 3 * NU + NP;
+    constexpr int NR = (NS + 255) / 256;
+    __shared__ cplx<Tin> lds[2][NS];
+    const int tid = threadIdx.x;
+    const int tx = tid % OTX, ty = tid / OTX;
+    const int x0 = blockIdx.x * OTX, y0 = blockIdx.y * OTY;
+    const int i = x0 + tx, j = y0 + ty;
+    const int n0 = o.dc.g[0], n1 = o.dc.g[1], n2 = o.dc.g[2];
+    const int planes = n2 + 1;
+    const int k = blockIdx.z % planes;
+    const int rlo = (blockIdx.z / planes) * rch, rhi = min(nrhs, rlo + rch);
+    const bool inx = i <= n0 && j <= n1;
+    int64_t sidx[NR];
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+        const int q = tid + it * 256;
+        int64_t v = -1;
+        if (q < 3 * NU) {
+            const int a = q / NU, e = q - a * NU;
+            const int ey = e / UW, ex = e - ey * UW;
+            const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+            const Dims& d = o.df[a];
+            if (gx >= 0 && gx < d.g[0] && gy >= 0 && gy < d.g[1] && k < d.g[2])
+                v = o.off[a] + ((int64_t)k * d.g[1] + gy) * d.g[0] + gx;
+        } else if (q < NS) {
+            const int e = q - 3 * NU;
+            const int ey = e / PW, ex = e - ey * PW;
+            const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+            if (gx >= 0 && gx < n0 && gy >= 0 && gy < n1 && k < n2)
+                v = o.off[3] + ((int64_t)k * n1 + gy) * n0 + gx;
+        }
+        sidx[it] = v;
+    }
+    const int ci[3] = {i, j, k};
+    const int nn[3] = {n0, n1, n2};
+    bool face[3];
+    int64_t fp[3], fsz[3];
+    FineCoef<double, 0, 3> cf[3];
+    c128 Dp[3];
+    bool zm[3], zp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const Dims& d = o.df[a];
+        bool ok = inx;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) if (b != a && ci[b] >= nn[b]) ok = false;
+        face[a] = ok;
+        fsz[a] = (int64_t)d.g[0] * d.g[1];
+        fp[a] = k * fsz[a] + (int64_t)j * d.g[0] + i;
+        zm[a] = ok && k > 0;
+        zp[a] = ok && k + 1 < d.g[2];
+        Dp[a] = mk(0.0, 0.0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) { cf[a].cp[b] = 0.0; cf[a].cm[b] = 0.0; }
+        if (ok) {
+            cf[a].load(d, i, j, k, fp[a], o.w[a][0], o.w[a][1], o.w[a][2], 0.0, 0.0, 0.0);
+            Dp[a] = o.D[a][fp[a]];
+        }
+    }
+    const bool cell = inx && i < n0 && j < n1 && k < n2;
+    const int64_t csz = (int64_t)n0 * n1;
+    const int64_t pc = k * csz + (int64_t)j * n0 + i;
+    const bool pzm = face[2] && k > 0;     // p in the cell below the own z-face
+    const double Cp = cell ? o.C[pc] : 0.0;
+    const int lu = (ty + 1) * UW + (tx + 1);
+    const int lp = 3 * NU + (ty + 1) * PW + (tx + 1);
+    cplx<Tin> vin[NR];
+    cplx<Tin> vzm[3], vzp[3], vpm;
+    auto load_in = [&](int r) {
+        const cplx<Tin>* xr = x + r * vs_in;
+#pragma unroll
+        for (int it = 0; it < NR; ++it) vin[it] = xr[sidx[it] >= 0 ? sidx[it] : 0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const cplx<Tin>* ur = xr + o.off[a];
+            vzm[a] = ur[zm[a] ? fp[a] - fsz[a] : 0];
+            vzp[a] = ur[zp[a] ? fp[a] + fsz[a] : 0];
+        }
+        vpm = xr[o.off[3] + (pzm ? pc - csz : 0)];
+    };
+    load_in(rlo);
+    for (int r = rlo; r < rhi; ++r) {
+        cplx<Tin>* S = lds[(r - rlo) & 1];
+#pragma unroll
+        for (int it = 0; it < NR; ++it) {
+            const int q = tid + it * 256;
+            if (q < NS) S[q] = sidx[it] >= 0 ? vin[it] : cplx<Tin>{Tin(0), Tin(0)};
+        }
+        c128 um2[3], up2[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            um2[a] = zm[a] ? ccast<double>(vzm[a]) : mk(0.0, 0.0);
+            up2[a] = zp[a] ? ccast<double>(vzp[a]) : mk(0.0, 0.0);
+        }
+        const c128 pm2 = pzm ? ccast<double>(vpm) : mk(0.0, 0.0);
+        if (r + 1 < rhi) load_in(r + 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        double rr = 0.0;
+        const c128 pcv = ccast<double>(S[lp]);
+        c128 div = mk(0.0, 0.0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!face[a]) continue;
+            const cplx<Tin>* U = S + a * NU;
+            const c128 uc = ccast<double>(U[lu]);
+            const c128 up[3] = {ccast<double>(U[lu + 1]), ccast<double>(U[lu + UW]), up2[a]};
+            const c128 um[3] = {ccast<double>(U[lu - 1]), ccast<double>(U[lu - UW]), um2[a]};
+            if (cell) div = div + o.ih[a] * (up[a] - uc);
+            c128 s = mk(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) s = s + cf[a].cp[b] * up[b] + cf[a].cm[b] * um[b];
+            // p at the cells on both sides of the face (zero ghost outside)
+            const c128 pnb = a == 2 ? pm2 : ccast<double>(S[lp - (a == 0 ? 1 : PW)]);
+            const c128 g = pcv - pnb;
+            c128 yv = Dp[a] * uc - s + o.ih[a] * g;
+            if (RES) {
+                yv = ra.b[r * vs_out + o.off[a] + fp[a]] - yv;
+                rr += yv.re * yv.re + yv.im * yv.im;
+            }
+            y[r * vs_out + o.off[a] + fp[a]] = yv;
+        }
+        if (cell) {
+            c128 yv = mk(-div.re - Cp * pcv.re, -div.im - Cp * pcv.im);
+            if (RES) {
+                yv = ra.b[r * vs_out + o.off[3] + pc] - yv;
+                rr += yv.re * yv.re + yv.im * yv.im;
+            }
+            y[r * vs_out + o.off[3] + pc] = yv;
+        }
+        if (RES) res_partial(ra, r, k, rr);
     }
 }
 

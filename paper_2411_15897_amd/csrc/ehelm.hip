@@ -1559,13 +1559,12 @@ void maybe_autotune(eh_ctx* c, int nrhs) {
 // operator and preconditioner
 
 // Workgroups of one operator application over the grid of (n1+1) x (n2+1)
-// (x (n3+1)) points: k_op2_lds tiles of OTX x OTY points in 2D, k_op's
-// 64 x 4 blocks per plane in 3D.
+// (x (n3+1)) points: tiles of OTX x OTY points (per plane in 3D).
 inline dim3 op_grid(const eh_ctx* c) {
     Dims e = c->dcell;
     for (int a = 0; a < c->dim; ++a) e.g[a] += 1;
-    if (c->dim == 2) return dim3((unsigned)((e.g[0] + OTX - 1) / OTX), (unsigned)((e.g[1] + OTY - 1) / OTY), 1);
-    return grid_of(e);
+    return dim3((unsigned)((e.g[0] + OTX - 1) / OTX), (unsigned)((e.g[1] + OTY - 1) / OTY),
+                (unsigned)(c->dim == 3 ? e.g[2] : 1));
 }
 inline int op_blocks(const eh_ctx* c) {
     const dim3 g = op_grid(c);
@@ -1594,7 +1593,8 @@ void launch_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrh
         hipLaunchKernelGGL((k_op2_lds<Tin, RES>), gc, dim3(256), 0, c->s, o, (const cplx<Tin>*)x, y, nrhs, vx, vy, ra,
                            rch);
     else
-        hipLaunchKernelGGL((k_op<Tin, 3, RES>), gc, kBlock, 0, c->s, o, (const cplx<Tin>*)x, y, nrhs, vx, vy, ra, rch);
+        hipLaunchKernelGGL((k_op3_lds<Tin, RES>), gc, dim3(256), 0, c->s, o, (const cplx<Tin>*)x, y, nrhs, vx, vy, ra,
+                           rch);
     HIPCHK(hipGetLastError());
 }
 
