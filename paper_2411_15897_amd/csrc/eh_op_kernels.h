@@ -97,6 +97,56 @@ struct DotArgs {
 
 constexpr int OTX = 64, OTY = 4;
 constexpr int OP_MAXJ = 32;
+
+// The DOTS epilogue for right-hand side r: the thread's NE degrees of
+// freedom (has[e], at index at[e] within a vector) with w values yk[e];
+// writes the workgroup's partials for columns t < J at workgroup index blk
+// of nt.  Called by every thread of the workgroup (two barriers).
+template <int NE>
+__device__ __forceinline__ void gs_first_pass(const DotArgs& da, int r, int64_t vs, const bool* has,
+                                              const int64_t* at, const c128* yk, int64_t blk, int64_t nt) {
+    __shared__ double red[4][4 * OP_MAXJ];
+    const int tid = threadIdx.x;
+    const int J = da.J;
+    const int lane = tid & 63, wave = tid >> 6;
+    const c128* Vl = da.V + (int64_t)(J - 1) * da.vstep + r * vs;
+    c128 vl[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) vl[e] = has[e] ? Vl[at[e]] : mk(0.0, 0.0);
+    for (int t = 0; t < J; ++t) {
+        const c128* Vt = da.V + (int64_t)t * da.vstep + r * vs;
+        double ar = 0.0, ai = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const c128 v = t == J - 1 ? vl[e] : (has[e] ? Vt[at[e]] : mk(0.0, 0.0));
+            ar += v.re * yk[e].re + v.im * yk[e].im;
+            ai += v.re * yk[e].im - v.im * yk[e].re;
+            gr += v.re * vl[e].re + v.im * vl[e].im;
+            gi += v.re * vl[e].im - v.im * vl[e].re;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            ar += __shfl_xor(ar, off, 64);
+            ai += __shfl_xor(ai, off, 64);
+            gr += __shfl_xor(gr, off, 64);
+            gi += __shfl_xor(gi, off, 64);
+        }
+        if (lane == 0) {
+            red[wave][4 * t] = ar;
+            red[wave][4 * t + 1] = ai;
+            red[wave][4 * t + 2] = gr;
+            red[wave][4 * t + 3] = gi;
+        }
+    }
+    __syncthreads();
+    if (tid < 2 * J) {
+        const int t = tid % J, g = tid / J;   // g = 0: conj(V_t) w, 1: conj(V_t) V_{J-1}
+        const int q = 4 * t + 2 * g;
+        const double sr = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+        const double si = (red[0][q + 1] + red[1][q + 1]) + (red[2][q + 1] + red[3][q + 1]);
+        da.partial[((int64_t)r * 2 * J + g * J + t) * nt + blk] = mk(sr, si);
+    }
+    __syncthreads();   // red is reused by the next right-hand side
+}
 template <class Tin, bool RES, bool DOTS = false>
 __global__ void __launch_bounds__(256)
 k_op2_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int nrhs, int64_t vs_in, int64_t vs_out,
@@ -211,50 +261,10 @@ k_op2_lds(OpArgs o, const cplx<Tin>* __restrict__ x, c128* __restrict__ y, int n
         }
         if (RES) res_partial(ra, r, 0, rr);
         if (DOTS) {
-            __shared__ double red[4][4 * OP_MAXJ];
-            const int J = da.J;
-            const int lane = tid & 63, wave = tid >> 6;
             const bool has[3] = {face[0], face[1], cell};
             const int64_t at[3] = {o.off[0] + fp[0], o.off[1] + fp[1], o.off[2] + pc};
-            const c128* Vl = da.V + (int64_t)(J - 1) * da.vstep + r * vs_out;
-            c128 vl[3];
-#pragma unroll
-            for (int e = 0; e < 3; ++e) vl[e] = has[e] ? Vl[at[e]] : mk(0.0, 0.0);
-            for (int t = 0; t < J; ++t) {
-                const c128* Vt = da.V + (int64_t)t * da.vstep + r * vs_out;
-                double ar = 0.0, ai = 0.0, gr = 0.0, gi = 0.0;
-#pragma unroll
-                for (int e = 0; e < 3; ++e) {
-                    const c128 v = t == J - 1 ? vl[e] : (has[e] ? Vt[at[e]] : mk(0.0, 0.0));
-                    ar += v.re * yk[e].re + v.im * yk[e].im;
-                    ai += v.re * yk[e].im - v.im * yk[e].re;
-                    gr += v.re * vl[e].re + v.im * vl[e].im;
-                    gi += v.re * vl[e].im - v.im * vl[e].re;
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    ar += __shfl_xor(ar, off, 64);
-                    ai += __shfl_xor(ai, off, 64);
-                    gr += __shfl_xor(gr, off, 64);
-                    gi += __shfl_xor(gi, off, 64);
-                }
-                if (lane == 0) {
-                    red[wave][4 * t] = ar;
-                    red[wave][4 * t + 1] = ai;
-                    red[wave][4 * t + 2] = gr;
-                    red[wave][4 * t + 3] = gi;
-                }
-            }
-            __syncthreads();
-            if (tid < 2 * J) {
-                const int t = tid % J, g = tid / J;   // g = 0: conj(V_t) w, 1: conj(V_t) V_{J-1}
-                const int q = 4 * t + 2 * g;
-                const double sr = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
-                const double si = (red[0][q + 1] + red[1][q + 1]) + (red[2][q + 1] + red[3][q + 1]);
-                const int64_t nt = (int64_t)gridDim.x * gridDim.y;
-                const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-                da.partial[((int64_t)r * 2 * J + g * J + t) * nt + blk] = mk(sr, si);
-            }
-            __syncthreads();   // red is reused by the next right-hand side
+            const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+            gs_first_pass<3>(da, r, vs_out, has, at, yk, blk, (int64_t)gridDim.x * gridDim.y);
         }
     }
 }

@@ -1607,10 +1607,13 @@ void apply_H(eh_ctx* c, const void* x, int64_t vx, c128* y, int64_t vy, int nrhs
 }
 
 // w = H z for nrhs vectors in the multigrid precision and, from the same
-// launch (2D), the first Gram-Schmidt pass of the Arnoldi step: d1 row r =
+// launch, the first Gram-Schmidt pass of the Arnoldi step: d1 row r =
 // [conj(V_t) . w for t < J, conj(V_t) . V_{J-1} for t < J] with basis
-// column t of RHS r at V + t * vstep + r * ndof.  Returns false in 3D,
-// where the caller runs the pass over w itself.
+// column t of RHS r at V + t * vstep + r * ndof.  2D only: in 3D the plane
+// kernel with the pass folded in measured slower than the two launches
+// (192^3 x 4: 486 against 461 ms per solve for operator and Krylov work),
+// so there, and for more columns than the launch handles, it returns false
+// (nothing launched).
 template <class Tin>
 bool apply_H_dots(eh_ctx* c, const void* z, c128* w, int nrhs, const c128* V, int64_t vstep, int J, c128* d1) {
     if (c->dim != 2 || J > OP_MAXJ) return false;
@@ -1637,8 +1640,8 @@ bool apply_H_dots(eh_ctx* c, const void* z, c128* w, int nrhs, const c128* V, in
     hipLaunchKernelGGL((k_op2_lds<Tin, false, true>), gc, dim3(256), 0, c->s, o, (const cplx<Tin>*)z, w, nrhs,
                        c->ndof, c->ndof, ResArgs{}, rch, da);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_partials, dim3(2 * J, nrhs), dim3(256), 0, c->s, (int)(g.x * g.y), 2 * J, nrhs,
-                       c->partial, d1);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(2 * J, nrhs), dim3(256), 0, c->s, (int)(g.x * g.y * g.z), 2 * J,
+                       nrhs, c->partial, d1);
     HIPCHK(hipGetLastError());
     return true;
 }
