@@ -205,9 +205,8 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload, config=None):
     WRITE_SIZE rocprofv3 counter run (KiB per dispatch), each scaled by what
     the same counter reads for the 1 GiB calibration copy of the same run
     (the run's first copy dispatch: it precedes the solver's own copies).
-    Only the run's last solve counts: the dispatches after the last copy
-    (each solve starts by copying b into the first basis column and copies
-    nothing else), so set-up and tuning launches do not enter."""
+    Only the run's last solve counts: the dispatches from its SOLVE_MARK
+    dispatch on, so set-up and tuning launches do not enter."""
     import csv
     members, leads = CLASS_KERNELS[kernel]
     leads = leads or members
@@ -222,8 +221,11 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload, config=None):
                              "--copy-calibration and at least one solve has two or more")
         ref = copies[0][1]                              # the 1 GiB calibration copy
         scale = (1 << 30) / 1024.0 / ref
-        last = copies[-1][0]                            # start of the last solve
-        cls = [r for r in rows if int(r["Dispatch_Id"]) > last and any(m in r["Kernel_Name"] for m in members)]
+        marks = [int(r["Dispatch_Id"]) for r in rows if SOLVE_MARK in r["Kernel_Name"]]
+        if not marks:
+            raise SystemExit(f"bench.py: {path} holds no {SOLVE_MARK} dispatch (no solve)")
+        last = max(marks)                               # start of the last solve
+        cls = [r for r in rows if int(r["Dispatch_Id"]) >= last and any(m in r["Kernel_Name"] for m in members)]
         nlaunch = sum(1 for r in cls if any(m in r["Kernel_Name"] for m in leads))
         kib = sum(float(r["Counter_Value"]) for r in cls) / max(nlaunch, 1)
         rec[f"{tag}_kib_per_launch_raw"] = kib
@@ -233,7 +235,7 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload, config=None):
         rec[f"dispatches_{tag}"] = len(cls)
         total += kib * scale * 1024.0
     rec["copy_reference"] = "torch copy of 1 GiB (__amd_rocclr_copyBuffer) in the same runs"
-    rec["launches_counted"] = "the dispatches of the run's last solve (after its last copy)"
+    rec["launches_counted"] = "the dispatches of the run's last solve (from its first Gram-Schmidt norm on)"
     rec["traffic_bytes_per_launch"] = total
     rec["source_files"] = CLASS_SOURCES.get(kernel, DEFAULT_SOURCES)
     rec["source_sha256"] = sources_sha256(rec["source_files"])
@@ -250,18 +252,24 @@ def pmc_summary(fetch_csv, write_csv, kernel, workload, config=None):
     return rec
 
 
+# Each solve's first cycle start, and nothing else in a benchmark run, takes
+# the norm of b with the Gram-Schmidt kernel's mode 3: its dispatches mark
+# where the solves begin in a trace or a counter run.
+SOLVE_MARK = "eh::k_gs<3>"
+
+
 def trace_summary(trace_csv, solves):
     """Per kernel class (and the vcycle group): launches and average
     duration over the last `solves` solves of a rocprofv3 --kernel-trace
     run of this script with --no-fp64 --no-cpu-baseline (its last solves
-    are the event-timed ones; each solve starts with its one copy)."""
+    are the event-timed ones; each begins at its SOLVE_MARK dispatch)."""
     import csv
     rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
-    copies = [i for i, r in enumerate(rows) if "__amd_rocclr_copyBuffer" in r["Kernel_Name"]]
-    if solves < 1 or len(copies) < solves:
-        raise SystemExit(f"bench.py: {trace_csv} holds {len(copies)} solves (copy dispatches), "
+    starts = [i for i, r in enumerate(rows) if SOLVE_MARK in r["Kernel_Name"]]
+    if solves < 1 or len(starts) < solves:
+        raise SystemExit(f"bench.py: {trace_csv} holds {len(starts)} solves ({SOLVE_MARK} dispatches), "
                          f"fewer than --steps {solves}")
-    tail = rows[copies[-solves] + 1:]
+    tail = rows[starts[-solves]:]
     out = {}
     for k, (members, leads) in CLASS_KERNELS.items():
         leads = leads or members
