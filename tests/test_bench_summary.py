@@ -1,9 +1,10 @@
 """bench.py's counter and trace summarisers on small synthetic files (no
 GPU): the 1 GiB calibration copy (the run's first copy, not a later larger
 one) fixes the scale of each counter, only the last solve's dispatches of a
-class (after the run's last copy) are summed and divided by its timed
-launches (a Gram-Schmidt pass is two dispatches), and the record carries
-the hash of the kernel sources."""
+class (from the solve's one cycle-start norm, eh::k_gs<3>, on; copies
+inside a solve do not cut it) are summed and divided by its timed launches
+(a Gram-Schmidt pass is two dispatches), and the record carries the hash of
+the kernel sources."""
 import csv
 import os
 
@@ -23,21 +24,24 @@ def _write(path, counter, rows):
 def test_pmc_summary_scales_by_the_copy_and_counts_timed_launches(tmp_path):
     gib_kib = (1 << 30) / 1024.0
     tune = ("void eh::k_fup<float, true, 2, 1>(eh::GArgs<float>, int)", 7777.0)   # set-up / tuning
+    norm = ("void eh::k_gs<3>(long, int)", 0.0)                  # a solve's first cycle start
     fetch = [("__amd_rocclr_copyBuffer", gib_kib / 2),          # the counter reads half
              tune,
-             ("__amd_rocclr_copyBuffer", gib_kib),               # an earlier solve starts
+             ("__amd_rocclr_copyBuffer", gib_kib), norm,         # an earlier solve starts
              ("void eh::k_gs<4>(long, int)", 3000.0), tune,
-             ("__amd_rocclr_copyBuffer", 2 * gib_kib),           # the last solve starts (larger copy)
+             ("__amd_rocclr_copyBuffer", 2 * gib_kib), norm,     # the last solve starts (larger copy)
              ("void eh::k_gs<4>(long, int)", 1000.0), ("eh::k_reduce_partials(int)", 10.0),
+             ("__amd_rocclr_copyBuffer", 3.0),                   # a copy inside the solve
              ("void eh::k_gs<2>(long, int)", 2000.0), ("eh::k_reduce_partials(int)", 10.0),
              ("void eh::k_fup<float, true, 2, 0>(eh::GArgs<float>, int)", 5000.0),
              ("void eh::k_gdense<float, 1>(eh::DenseArgs, eh::GArgs<float>)", 300.0)]
     write = [("__amd_rocclr_copyBuffer", gib_kib),
              tune,
-             ("__amd_rocclr_copyBuffer", gib_kib),
+             ("__amd_rocclr_copyBuffer", gib_kib), norm,
              ("void eh::k_gs<4>(long, int)", 3000.0), tune,
-             ("__amd_rocclr_copyBuffer", 2 * gib_kib),
+             ("__amd_rocclr_copyBuffer", 2 * gib_kib), norm,
              ("void eh::k_gs<4>(long, int)", 0.0), ("eh::k_reduce_partials(int)", 1.0),
+             ("__amd_rocclr_copyBuffer", 3.0),
              ("void eh::k_gs<2>(long, int)", 500.0), ("eh::k_reduce_partials(int)", 1.0),
              ("void eh::k_fup<float, true, 2, 0>(eh::GArgs<float>, int)", 900.0),
              ("void eh::k_gdense<float, 1>(eh::DenseArgs, eh::GArgs<float>)", 100.0)]
@@ -45,9 +49,10 @@ def test_pmc_summary_scales_by_the_copy_and_counts_timed_launches(tmp_path):
     _write(f, "FETCH_SIZE", fetch)
     _write(w, "WRITE_SIZE", write)
     rec = bench.pmc_summary(str(f), str(w), "krylov", "test")
-    assert rec["launches_fetch"] == 2 and rec["dispatches_fetch"] == 4
+    assert rec["launches_fetch"] == 3 and rec["dispatches_fetch"] == 5
     assert abs(rec["fetch_scale"] - 2.0) < 1e-12 and abs(rec["write_scale"] - 1.0) < 1e-12
-    expect = ((1000 + 10 + 2000 + 10) / 2 * 2.0 + (0 + 1 + 500 + 1) / 2 * 1.0) * 1024.0
+    # the last solve's krylov class: its norm, two passes and their reductions (three timed launches)
+    expect = ((0 + 1000 + 10 + 2000 + 10) / 3 * 2.0 + (0 + 0 + 1 + 500 + 1) / 3 * 1.0) * 1024.0
     assert abs(rec["traffic_bytes_per_launch"] - expect) < 1e-6
     assert rec["source_sha256"] == bench.sources_sha256(rec["source_files"])
     up = bench.pmc_summary(str(f), str(w), "fine_up", "test")
@@ -60,12 +65,16 @@ def test_pmc_summary_scales_by_the_copy_and_counts_timed_launches(tmp_path):
 
 def test_trace_summary_counts_the_last_solves(tmp_path):
     """Launch counts and mean durations over the last K solves of a kernel
-    trace (each solve opens with its copy; earlier launches are ignored)."""
+    trace (each solve opens with its copy and its cycle-start norm; copies
+    inside a solve do not cut it; earlier launches are ignored)."""
     import csv as _csv
     rows = [("__amd_rocclr_copyBuffer", 5), ("void eh::k_fup<float, true, 2, 1>(x)", 999),
-            ("__amd_rocclr_copyBuffer", 5), ("void eh::k_fup<float, true, 2, 0>(x)", 20),
+            ("__amd_rocclr_copyBuffer", 5), ("void eh::k_gs<3>(long, int)", 2),
+            ("void eh::k_fup<float, true, 2, 0>(x)", 20),
             ("void eh::k_gs<4>(long, int)", 30), ("eh::k_reduce_partials(int)", 4),
-            ("__amd_rocclr_copyBuffer", 5), ("void eh::k_fup<float, false, 2, 0>(x)", 10),
+            ("__amd_rocclr_copyBuffer", 5), ("void eh::k_gs<3>(long, int)", 2),
+            ("void eh::k_fup<float, false, 2, 0>(x)", 10),
+            ("__amd_rocclr_copyBuffer", 5),
             ("void eh::k_fdown<float, true, 1>(x)", 12)]
     path = tmp_path / "trace.csv"
     with open(path, "w", newline="") as fp:
@@ -79,7 +88,7 @@ def test_trace_summary_counts_the_last_solves(tmp_path):
     out = bench.trace_summary(str(path), 2)
     assert out["vcycle"]["launches"] == 3
     assert abs(out["vcycle"]["avg_us"] - (20 + 10 + 12) / 3) < 1e-9
-    assert out["krylov"]["launches"] == 1 and abs(out["krylov"]["avg_us"] - 34) < 1e-9
+    assert out["krylov"]["launches"] == 3 and abs(out["krylov"]["avg_us"] - (2 + 30 + 4 + 2) / 3) < 1e-9
     assert out["fine_up"]["launches"] == 1 and out["coarse_up"]["launches"] == 1
 
 
