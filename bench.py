@@ -140,6 +140,12 @@ TIMER_GROUPS = {"vcycle": VCYCLE_CLASSES}
 # rocprofv3 prints) and, where a timed launch spans several dispatches, the
 # ones that open a timed launch (a Gram-Schmidt pass is k_gs plus its
 # fixed-order reduction).
+def _gfine(*modes):
+    """Kernel names of the per-point fine-level sweeps of the given modes."""
+    return tuple(f"eh::k_gfine<{t}, {k}, {d}, {m}>" for m in modes for t in ("float", "double")
+                 for k in (0, 1, 2) for d in (2, 3))
+
+
 CLASS_KERNELS = {
     "krylov": (("eh::k_gs<", "eh::k_reduce_partials", "eh::k_xupdate<"), ("eh::k_gs<", "eh::k_xupdate<")),
     "fine_down": (("eh::k_fdown<float, true", "eh::k_fdown<double, true"), None),
@@ -147,6 +153,13 @@ CLASS_KERNELS = {
     "coarse_down": (("eh::k_fdown<float, false", "eh::k_fdown<double, false"), None),
     "coarse_up": (("eh::k_fup<float, false", "eh::k_fup<double, false"), None),
     "coarse": (("eh::k_gstencil<",), None),
+    "fine_sweep": (_gfine(1), None),
+    "fine_resid": (_gfine(2), None),
+    "fine_first": (_gfine(0, 4, 5), None),
+    "restrict": (("eh::k_gtransfer<float, 2, true>", "eh::k_gtransfer<float, 3, true>",
+                  "eh::k_gtransfer<double, 2, true>", "eh::k_gtransfer<double, 3, true>"), None),
+    "prolong": (("eh::k_gtransfer<float, 2, false>", "eh::k_gtransfer<float, 3, false>",
+                 "eh::k_gtransfer<double, 2, false>", "eh::k_gtransfer<double, 3, false>"), None),
     "operator": (("eh::k_op2_lds<", "eh::k_op3_lds<"), None),
     "distribute": (("eh::k_distribute<",), None),
     "couple": (("eh::k_gcouple<",), None),
@@ -311,8 +324,10 @@ def main():
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--restart", type=int, default=None)
-    ap.add_argument("--roofline-kernel", default="fine_up",
-                    help="kernel class (or the group vcycle: every multigrid kernel) for the roofline figure")
+    ap.add_argument("--roofline-kernel", default=None,
+                    help="kernel class (or the group vcycle: every multigrid kernel) for the roofline figure "
+                         "(default: fine_up, the fused fine up leg, in 2D; fine_sweep, the fine-level "
+                         "Jacobi sweep, in 3D)")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--cpu-procs", type=int, default=None,
                     help="processes of the RHS-parallel CPU baseline (default: min(16, host threads))")
@@ -332,8 +347,9 @@ def main():
         return
     if args.pmc_summary:
         import workloads as W
-        print(json.dumps(pmc_summary(*args.pmc_summary, args.roofline_kernel, W.config(args.config).name,
-                                     args.config), indent=1))
+        wl_ = W.config(args.config)
+        kernel_ = args.roofline_kernel or ("fine_up" if len(wl_.n) == 2 else "fine_sweep")
+        print(json.dumps(pmc_summary(*args.pmc_summary, kernel_, wl_.name, args.config), indent=1))
         return
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU only; several GPUs would each take a share of "
@@ -415,7 +431,7 @@ def main():
     s32 = make(32)
     torch.cuda.synchronize()
     log(f"setup (complex64 multigrid) {time.perf_counter() - t_setup:.2f} s")
-    kernel = args.roofline_kernel
+    kernel = args.roofline_kernel or ("fine_up" if len(wl.n) == 2 else "fine_sweep")
     split = {}
     split_bytes = {}
     # one untimed solve with every kernel class event-timed: the split of
