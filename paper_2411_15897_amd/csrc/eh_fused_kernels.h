@@ -17,16 +17,14 @@
 //             Each workgroup owns a tile of fine points.  u~ = u0 + P e over
 //             the tile plus nu2 stencil widths is staged in LDS; each
 //             damped Jacobi sweep runs from LDS on a region one stencil
-//             width smaller, and the last one writes the tile.  The coarse
-//             correction under the region is staged in LDS too, and a
-//             right-hand side's loads are issued while the previous one
-//             sweeps (up_body_fine on the fine level, up_body_coarse on the
-//             Galerkin levels).
+//             width smaller, and the last one writes the tile.  On the fine
+//             level the coarse correction under the region is staged in LDS
+//             too, and a right-hand side's loads are issued while the
+//             previous one sweeps (up_body_fine).
 //
 // The arithmetic per point is that of the unfused kernels (k_gfine,
-// k_gstencil, k_gtransfer) up to rounding: the order of summation inside a
-// stencil differs, and on the fine level the diagonal of a Jacobi update is
-// cancelled algebraically (PointOp).  Points outside the level's grid hold 0 in LDS, and every
+// k_gstencil, k_gtransfer); only the order of summation inside a stencil
+// can differ.  Points outside the level's grid hold 0 in LDS, and every
 // coupling towards them is 0 (the fine couplings by construction, the
 // Galerkin stencils because the setup never couples outside the grid), so
 // the stencil sums need no bounds tests.
@@ -61,10 +59,13 @@ constexpr FCfg kFUp[] = {{64, 16, 1024}, {64, 8, 512}, {32, 8, 256}, {16, 8, 128
 constexpr int kFCfgs = 4;
 
 constexpr int FUSE_MAXW = 2;
-// LDS elements of the down leg: staged u0 (support + halo) + residual of the
-// support (the up legs size theirs by FineUpGeom / CoarseUpGeom)
+// LDS elements: down = staged u0 (support + halo) + residual of the support;
+// up = u~ (tile + 2 halos) + first sweep (tile + 1 halo)
 __host__ __device__ constexpr int fd_lds(int cx, int cy) {
     return (2 * cx + 2 + 2 * FUSE_MAXW) * (2 * cy + 2 + 2 * FUSE_MAXW) + (2 * cx + 2) * (2 * cy + 2);
+}
+__host__ __device__ constexpr int fu_lds(int tx, int ty) {
+    return (tx + 4 * FUSE_MAXW) * (ty + 4 * FUSE_MAXW) + (tx + 2 * FUSE_MAXW) * (ty + 2 * FUSE_MAXW);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -377,6 +378,120 @@ k_fdown(GArgs<T> a, int nrhs, int rch) {
 // ---------------------------------------------------------------------------
 // up leg: a.d = level l, a.dc = level l+1, a.f = f_l (vf), a.u = e_{l+1}
 // (vu), a.out = e_l (vo)
+
+// Coarse levels (stored Galerkin stencils); the fine level has up_body_fine.
+template <class T, bool FINE, int KIND, int WX, int WY, int NM, int NU2, int TX, int TY, int NT, bool HALF>
+__device__ __forceinline__ void up_body(const GArgs<T>& a, int slot, cplx<T>* lds, int r0, int r1, int tile_x,
+                                        int tile_y) {
+    static_assert(TX * TY == NT, "one tile point per thread");
+    const Dims d = a.d[slot], dc = a.dc[slot];
+    const int nx = d.g[0], ny = d.g[1];
+    const int tx0 = tile_x * TX, ty0 = tile_y * TY;
+    if (tx0 >= nx || ty0 >= ny) return;           // uniform per workgroup
+    constexpr int HX = NU2 * WX, HY = NU2 * WY;
+    constexpr int AX = TX + 2 * HX, AY = TY + 2 * HY;     // u~
+    constexpr int BX = TX + 2 * WX, BY = TY + 2 * WY;     // first of two sweeps
+    constexpr int RING = BX * BY - TX * TY;               // its points outside the tile
+    static_assert(RING <= NT, "at most one ring point per thread");
+    // small operators (fine level, 3x3 stencils) of the ring point, and any
+    // operator in the small-tile configuration (meant for the small levels,
+    // where registers do not limit the few resident workgroups), are loaded
+    // up front with the own point's, so that every global load of the kernel
+    // is issued before the first barrier
+    constexpr bool RING_EARLY = FINE || (2 * WX + 1) * (2 * WY + 1) <= 9 || NT <= 128;
+    cplx<T>* A = lds;
+    cplx<T>* B = lds + AX * AY;
+    const int64_t csy = dc.g[0];
+    // this thread's tile point and its operator, kept for every sweep and RHS
+    const int my_y = threadIdx.x / TX, my_x = threadIdx.x - my_y * TX;
+    const int mgx = tx0 + my_x, mgy = ty0 + my_y;
+    const bool mine = mgx < nx && mgy < ny;
+    const int64_t mp = (int64_t)mgy * nx + mgx;
+    PointOp<T, FINE, KIND, WX, WY, HALF> op;
+    if (mine) op.load(a, slot, d, mgx, mgy, mp);
+    // this thread's ring point (first sweep only)
+    int rbx = 0, rby = 0;
+    {
+        const int q = threadIdx.x;
+        if (q < 2 * WY * BX) {                       // rows above and below the tile
+            const int row = q / BX;
+            rbx = q - row * BX;
+            rby = row < WY ? row : TY + row;
+        } else {                                     // columns left and right
+            const int q2 = q - 2 * WY * BX;
+            const int row = q2 / (2 * WX), cc = q2 - row * (2 * WX);
+            rby = WY + row;
+            rbx = cc < WX ? cc : TX + cc;
+        }
+    }
+    const int rgx = tx0 - WX + rbx, rgy = ty0 - WY + rby;
+    const bool ring = NU2 == 2 && (int)threadIdx.x < RING && rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny;
+    const int64_t rp = (int64_t)rgy * nx + rgx;
+    PointOp<T, FINE, KIND, WX, WY, HALF> rop;
+    if (RING_EARLY && ring) rop.load(a, slot, d, rgx, rgy, rp);
+    constexpr int NA = (AX * AY + NT - 1) / NT;    // at most 3 rounds
+    for (int r = r0; r < r1; ++r) {
+        const cplx<T>* __restrict__ f = a.f[slot] + r * a.vf[slot];
+        const cplx<T>* __restrict__ ec = a.u[slot] + r * a.vu[slot];
+        cplx<T>* __restrict__ out = a.out[slot] + r * a.vo[slot];
+        const cplx<T> fmine = mine ? f[mp] : czero<T>();
+        const cplx<T> fring = ring ? f[rp] : czero<T>();
+        if (r > r0) lds_barrier();
+        // u~ = w D^-1 f + P e over region A
+#pragma unroll 1
+        for (int it = 0; it < NA; ++it) {
+            const int q = threadIdx.x + it * NT;
+            if (q >= AX * AY) break;
+            const int ay = q / AX, ax = q - ay * AX;
+            const int gx = tx0 - HX + ax, gy = ty0 - HY + ay;
+            cplx<T> v = czero<T>();
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const int64_t p = (int64_t)gy * nx + gx;
+                int xi0, xi1, yi0, yi1;
+                float xw0, xw1, yw0, yw1;
+                p1<(NM & 1) != 0>(gx, dc.g[0], xi0, xi1, xw0, xw1);
+                p1<(NM & 2) != 0>(gy, dc.g[1], yi0, yi1, yw0, yw1);
+                const cplx<T> pe = (T(yw0) * T(xw0)) * ec[yi0 * csy + xi0] +
+                                   (T(yw0) * T(xw1)) * ec[yi0 * csy + xi1] +
+                                   (T(yw1) * T(xw0)) * ec[yi1 * csy + xi0] +
+                                   (T(yw1) * T(xw1)) * ec[yi1 * csy + xi1];
+                v = fuse_sc<T, FINE>(a, slot, p) * f[p] + pe;
+            }
+            A[q] = v;
+        }
+        lds_barrier();
+        if (NU2 == 2) {
+            // first sweep on the tile (own point) and on the ring around it
+            {
+                const int l = (my_y + 2 * WY) * AX + (my_x + 2 * WX);
+                cplx<T> v = czero<T>();
+                if (mine) v = op.template sweep<AX>(A, l, fmine);
+                B[(my_y + WY) * BX + my_x + WX] = v;
+            }
+            if ((int)threadIdx.x < RING) {
+                cplx<T> v = czero<T>();
+                const int l = (rby + WY) * AX + (rbx + WX);
+                if (ring && RING_EARLY) {
+                    v = rop.template sweep<AX>(A, l, fring);
+                } else if (ring) {
+                    // wide stencils: loaded here, not held across the batch
+                    PointOp<T, FINE, KIND, WX, WY, HALF> wop;
+                    wop.load(a, slot, d, rgx, rgy, rp);
+                    v = wop.template sweep<AX>(A, l, fring);
+                }
+                B[rby * BX + rbx] = v;
+            }
+            lds_barrier();
+        }
+        const cplx<T>* S = NU2 == 2 ? B : A;
+        constexpr int SX = NU2 == 2 ? BX : AX;
+        constexpr int OX = NU2 == 2 ? WX : HX, OY = NU2 == 2 ? WY : HY;
+        if (mine) {
+            const int l = (my_y + OY) * SX + (my_x + OX);
+            out[mp] = op.template sweep<SX>(S, l, fmine);
+        }
+    }
+}
 
 // Fine-level up leg.  Per right-hand side: the coarse correction e_{l+1}
 // under the tile's region is staged in LDS (one load per coarse point
@@ -759,6 +874,8 @@ k_fup(GArgs<T> a, int nrhs, int rch) {
     const int kind = a.kind[slot];
     int tx, ty;
     xcd_tile(tx, ty);
+#define EH_FU(FI, KI, WX, WY, NM, HF) \
+    up_body<T, FI, KI, WX, WY, NM, NU2, TX, TY, NT, HF>(a, slot, lds, r0, r1, tx, ty)
 #define EH_FUF(KI, NM) up_body_fine<T, KI, NM, NU2, TX, TY, NT>(a, slot, lds, r0, r1, tx, ty)
 #define EH_FUC(WX, WY, NM, HF) up_body_coarse<T, WX, WY, NM, NU2, TX, TY, NT, HF>(a, slot, lds, r0, r1, tx, ty)
     if (FINE) {
@@ -778,6 +895,7 @@ k_fup(GArgs<T> a, int nrhs, int rch) {
     }
 #undef EH_FUC
 #undef EH_FUF
+#undef EH_FU
 }
 
 }  // namespace eh
