@@ -141,9 +141,12 @@ TIMER_GROUPS = {"vcycle": VCYCLE_CLASSES}
 # ones that open a timed launch (a Gram-Schmidt pass is k_gs plus its
 # fixed-order reduction).
 def _gfine(*modes):
-    """Kernel names of the per-point fine-level sweeps of the given modes."""
-    return tuple(f"eh::k_gfine<{t}, {k}, {d}, {m}>" for m in modes for t in ("float", "double")
-                 for k in (0, 1, 2) for d in (2, 3))
+    """Kernel names of the fine-level sweeps of the given modes (per point,
+    and plane-staged in 3D)."""
+    return (tuple(f"eh::k_gfine<{t}, {k}, {d}, {m}>" for m in modes for t in ("float", "double")
+                  for k in (0, 1, 2) for d in (2, 3))
+            + tuple(f"eh::k_gfine3_lds<{t}, {k}, {m}>" for m in modes for t in ("float", "double")
+                    for k in (0, 1, 2)))
 
 
 CLASS_KERNELS = {
@@ -168,12 +171,14 @@ CLASS_KERNELS = {
     "vcycle": (("eh::k_fdown<", "eh::k_fup<", "eh::k_gdense<", "eh::k_gstencil<", "eh::k_gfine<",
                 "eh::k_gtransfer<", "eh::k_bt_fwd<", "eh::k_bt_back<"), None),
 }
-CLASS_SOURCES = {
-    "krylov": ["paper_2411_15897_amd/csrc/eh_krylov_kernels.h", "paper_2411_15897_amd/csrc/eh_common.h"],
-}
 DEFAULT_SOURCES = ["paper_2411_15897_amd/csrc/eh_fused_kernels.h", "paper_2411_15897_amd/csrc/eh_group_kernels.h",
                    "paper_2411_15897_amd/csrc/eh_mg_kernels.h", "paper_2411_15897_amd/csrc/eh_op_kernels.h",
                    "paper_2411_15897_amd/csrc/eh_common.h"]
+_FINE3 = DEFAULT_SOURCES + ["paper_2411_15897_amd/csrc/eh_fine3_kernels.h"]
+CLASS_SOURCES = {
+    "krylov": ["paper_2411_15897_amd/csrc/eh_krylov_kernels.h", "paper_2411_15897_amd/csrc/eh_common.h"],
+    "fine_sweep": _FINE3, "fine_resid": _FINE3, "fine_first": _FINE3, "vcycle": _FINE3,
+}
 
 
 

@@ -22,6 +22,7 @@
 #include "eh_krylov_kernels.h"
 #include "eh_mg_kernels.h"
 #include "eh_op_kernels.h"
+#include "eh_fine3_kernels.h"
 #include "eh_setup_kernels.h"
 #include "eh_grad_kernels.h"
 #include "eh_group_kernels.h"
@@ -904,6 +905,25 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
                           : (mode == 0 || mode == 4 || mode == 5 ? KC_FINE_FIRST
                                                                   : (mode == 1 ? KC_FINE_SWEEP : KC_FINE_RESID));
     Timed tm(c, cls, by);
+    if (l == 0 && c->dim == 3 && (mode == 1 || mode == 2 || mode == 5)) {
+        // the plane-staged kernel: FTX x FTY tiles of 256 threads
+        int gx = 1, gy = 1;
+        for (int s = 0; s < a.ns; ++s) {
+            gx = std::max(gx, (a.d[s].g[0] + FTX - 1) / FTX);
+            gy = std::max(gy, (a.d[s].g[1] + FTY - 1) / FTY);
+        }
+        const int rch = rhs_chunk(gx * gy * a.maxg2, a.ns, nrhs);
+        const int nch = (std::max(nrhs, 1) + rch - 1) / rch;
+        const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)(a.maxg2 * a.ns * nch));
+#define EH_G3(KIND)                                                                                              \
+    if (mode == 1) hipLaunchKernelGGL((k_gfine3_lds<T, KIND, 1>), g, dim3(256), 0, c->s, a, nrhs, rch);          \
+    else if (mode == 2) hipLaunchKernelGGL((k_gfine3_lds<T, KIND, 2>), g, dim3(256), 0, c->s, a, nrhs, rch);     \
+    else hipLaunchKernelGGL((k_gfine3_lds<T, KIND, 5>), g, dim3(256), 0, c->s, a, nrhs, rch);
+        if (P && a.tilde) { EH_G3(2) } else if (P) { EH_G3(1) } else { EH_G3(0) }
+#undef EH_G3
+        HIPCHK(hipGetLastError());
+        return;
+    }
     const dim3 blk = shape_block(c, group_of(c, kind0), l, 0);
     int rch = 1;
     const dim3 g = ggrid(a, blk, nrhs, rch);
