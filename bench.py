@@ -155,7 +155,7 @@ CLASS_KERNELS = {
     "fine_up": (("eh::k_fup<float, true", "eh::k_fup<double, true"), None),
     "coarse_down": (("eh::k_fdown<float, false", "eh::k_fdown<double, false"), None),
     "coarse_up": (("eh::k_fup<float, false", "eh::k_fup<double, false"), None),
-    "coarse": (("eh::k_gstencil<",), None),
+    "coarse": (("eh::k_gstencil<", "eh::k_gstencil3_lds<"), None),
     "fine_sweep": (_gfine(1), None),
     "fine_resid": (_gfine(2), None),
     "fine_first": (_gfine(0, 4, 5), None),
@@ -169,15 +169,18 @@ CLASS_KERNELS = {
     "dense": (("eh::k_gdense<", "eh::k_bt_fwd<", "eh::k_bt_back<"), None),
     # every timed multigrid kernel: the V-cycles of the three (four) blocks
     "vcycle": (("eh::k_fdown<", "eh::k_fup<", "eh::k_gdense<", "eh::k_gstencil<", "eh::k_gfine<",
-                "eh::k_gtransfer<", "eh::k_bt_fwd<", "eh::k_bt_back<"), None),
+                "eh::k_gtransfer<", "eh::k_bt_fwd<", "eh::k_bt_back<", "eh::k_gfine3_lds<",
+                "eh::k_gstencil3_lds<"), None),
 }
 DEFAULT_SOURCES = ["paper_2411_15897_amd/csrc/eh_fused_kernels.h", "paper_2411_15897_amd/csrc/eh_group_kernels.h",
                    "paper_2411_15897_amd/csrc/eh_mg_kernels.h", "paper_2411_15897_amd/csrc/eh_op_kernels.h",
                    "paper_2411_15897_amd/csrc/eh_common.h"]
 _FINE3 = DEFAULT_SOURCES + ["paper_2411_15897_amd/csrc/eh_fine3_kernels.h"]
+_STENCIL3 = DEFAULT_SOURCES + ["paper_2411_15897_amd/csrc/eh_stencil3_kernels.h"]
 CLASS_SOURCES = {
     "krylov": ["paper_2411_15897_amd/csrc/eh_krylov_kernels.h", "paper_2411_15897_amd/csrc/eh_common.h"],
-    "fine_sweep": _FINE3, "fine_resid": _FINE3, "fine_first": _FINE3, "vcycle": _FINE3,
+    "fine_sweep": _FINE3, "fine_resid": _FINE3, "fine_first": _FINE3, "coarse": _STENCIL3,
+    "vcycle": _FINE3 + ["paper_2411_15897_amd/csrc/eh_stencil3_kernels.h"],
 }
 
 

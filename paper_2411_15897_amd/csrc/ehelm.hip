@@ -23,6 +23,7 @@
 #include "eh_mg_kernels.h"
 #include "eh_op_kernels.h"
 #include "eh_fine3_kernels.h"
+#include "eh_stencil3_kernels.h"
 #include "eh_setup_kernels.h"
 #include "eh_grad_kernels.h"
 #include "eh_group_kernels.h"
@@ -921,6 +922,17 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
     else hipLaunchKernelGGL((k_gfine3_lds<T, KIND, 5>), g, dim3(256), 0, c->s, a, nrhs, rch);
         if (P && a.tilde) { EH_G3(2) } else if (P) { EH_G3(1) } else { EH_G3(0) }
 #undef EH_G3
+        HIPCHK(hipGetLastError());
+        return;
+    }
+    if (l > 0 && c->dim == 3 && a.mixed && (mode == 1 || mode == 2 || mode == 5)) {
+        // the plane-staged 27-point kernel: STX x STY tiles of 256 threads
+        const dim3 blk(STX, STY, 1);
+        int rch = 1;
+        const dim3 g = ggrid(a, blk, nrhs, rch);
+        if (mode == 1) hipLaunchKernelGGL((k_gstencil3_lds<T, 1>), g, dim3(256), 0, c->s, a, nrhs, rch);
+        else if (mode == 2) hipLaunchKernelGGL((k_gstencil3_lds<T, 2>), g, dim3(256), 0, c->s, a, nrhs, rch);
+        else hipLaunchKernelGGL((k_gstencil3_lds<T, 5>), g, dim3(256), 0, c->s, a, nrhs, rch);
         HIPCHK(hipGetLastError());
         return;
     }
