@@ -160,9 +160,11 @@ CLASS_KERNELS = {
     "fine_resid": (_gfine(2), None),
     "fine_first": (_gfine(0, 4, 5), None),
     "restrict": (("eh::k_gtransfer<float, 2, true>", "eh::k_gtransfer<float, 3, true>",
-                  "eh::k_gtransfer<double, 2, true>", "eh::k_gtransfer<double, 3, true>"), None),
+                  "eh::k_gtransfer<double, 2, true>", "eh::k_gtransfer<double, 3, true>",
+                  "eh::k_grestrict3_lds<"), None),
     "prolong": (("eh::k_gtransfer<float, 2, false>", "eh::k_gtransfer<float, 3, false>",
-                 "eh::k_gtransfer<double, 2, false>", "eh::k_gtransfer<double, 3, false>"), None),
+                 "eh::k_gtransfer<double, 2, false>", "eh::k_gtransfer<double, 3, false>",
+                 "eh::k_gprolong3_lds<"), None),
     "operator": (("eh::k_op2_lds<", "eh::k_op3_lds<"), None),
     "distribute": (("eh::k_distribute<",), None),
     "couple": (("eh::k_gcouple<",), None),
@@ -170,17 +172,20 @@ CLASS_KERNELS = {
     # every timed multigrid kernel: the V-cycles of the three (four) blocks
     "vcycle": (("eh::k_fdown<", "eh::k_fup<", "eh::k_gdense<", "eh::k_gstencil<", "eh::k_gfine<",
                 "eh::k_gtransfer<", "eh::k_bt_fwd<", "eh::k_bt_back<", "eh::k_gfine3_lds<",
-                "eh::k_gstencil3_lds<"), None),
+                "eh::k_gstencil3_lds<", "eh::k_grestrict3_lds<", "eh::k_gprolong3_lds<"), None),
 }
 DEFAULT_SOURCES = ["paper_2411_15897_amd/csrc/eh_fused_kernels.h", "paper_2411_15897_amd/csrc/eh_group_kernels.h",
                    "paper_2411_15897_amd/csrc/eh_mg_kernels.h", "paper_2411_15897_amd/csrc/eh_op_kernels.h",
                    "paper_2411_15897_amd/csrc/eh_common.h"]
 _FINE3 = DEFAULT_SOURCES + ["paper_2411_15897_amd/csrc/eh_fine3_kernels.h"]
 _STENCIL3 = DEFAULT_SOURCES + ["paper_2411_15897_amd/csrc/eh_stencil3_kernels.h"]
+_TRANSFER3 = DEFAULT_SOURCES + ["paper_2411_15897_amd/csrc/eh_transfer3_kernels.h"]
 CLASS_SOURCES = {
     "krylov": ["paper_2411_15897_amd/csrc/eh_krylov_kernels.h", "paper_2411_15897_amd/csrc/eh_common.h"],
     "fine_sweep": _FINE3, "fine_resid": _FINE3, "fine_first": _FINE3, "coarse": _STENCIL3,
-    "vcycle": _FINE3 + ["paper_2411_15897_amd/csrc/eh_stencil3_kernels.h"],
+    "restrict": _TRANSFER3, "prolong": _TRANSFER3,
+    "vcycle": _FINE3 + ["paper_2411_15897_amd/csrc/eh_stencil3_kernels.h",
+                        "paper_2411_15897_amd/csrc/eh_transfer3_kernels.h"],
 }
 
 

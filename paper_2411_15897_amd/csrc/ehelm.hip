@@ -24,6 +24,7 @@
 #include "eh_op_kernels.h"
 #include "eh_fine3_kernels.h"
 #include "eh_stencil3_kernels.h"
+#include "eh_transfer3_kernels.h"
 #include "eh_setup_kernels.h"
 #include "eh_grad_kernels.h"
 #include "eh_group_kernels.h"
@@ -863,6 +864,19 @@ dim3 ggrid(const GArgs<T>& a, const dim3& blk, int nrhs, int& rch) {
 template <class T>
 void launch_transfer(eh_ctx* c, const GArgs<T>& t, const dim3& blk, bool restrict_to_coarse, int nrhs) {
     int rch = 1;
+    if (c->dim == 3) {
+        // the staged 3D transfers: tiles of 256 threads
+        if (restrict_to_coarse) {
+            const dim3 g = ggrid(t, dim3(RTX, RTY, 1), nrhs, rch);
+            if (t.mixed) hipLaunchKernelGGL((k_grestrict3_lds<T, true>), g, dim3(256), 0, c->s, t, nrhs, rch);
+            else hipLaunchKernelGGL((k_grestrict3_lds<T, false>), g, dim3(256), 0, c->s, t, nrhs, rch);
+        } else {
+            const dim3 g = ggrid(t, dim3(PTX, PTY, 1), nrhs, rch);
+            hipLaunchKernelGGL((k_gprolong3_lds<T>), g, dim3(256), 0, c->s, t, nrhs, rch);
+        }
+        HIPCHK(hipGetLastError());
+        return;
+    }
     const dim3 g = ggrid(t, blk, nrhs, rch);
     if (restrict_to_coarse) {
         if (c->dim == 2) hipLaunchKernelGGL((k_gtransfer<T, 2, true>), g, blk, 0, c->s, t, nrhs, rch);
