@@ -168,10 +168,10 @@ CLASS_KERNELS = {
     "operator": (("eh::k_op2_lds<", "eh::k_op3_lds<"), None),
     "distribute": (("eh::k_distribute<",), None),
     "couple": (("eh::k_gcouple<",), None),
-    "dense": (("eh::k_gdense<", "eh::k_bt_fwd<", "eh::k_bt_back<"), None),
+    "dense": (("eh::k_gdense<", "eh::k_bt_fpart<", "eh::k_bt_chain<"), None),
     # every timed multigrid kernel: the V-cycles of the three (four) blocks
     "vcycle": (("eh::k_fdown<", "eh::k_fup<", "eh::k_gdense<", "eh::k_gstencil<", "eh::k_gfine<",
-                "eh::k_gtransfer<", "eh::k_bt_fwd<", "eh::k_bt_back<", "eh::k_gfine3_lds<",
+                "eh::k_gtransfer<", "eh::k_bt_fpart<", "eh::k_bt_chain<", "eh::k_gfine3_lds<",
                 "eh::k_gstencil3_lds<", "eh::k_grestrict3_lds<", "eh::k_gprolong3_lds<"), None),
 }
 DEFAULT_SOURCES = ["paper_2411_15897_amd/csrc/eh_fused_kernels.h", "paper_2411_15897_amd/csrc/eh_group_kernels.h",
@@ -184,8 +184,10 @@ CLASS_SOURCES = {
     "krylov": ["paper_2411_15897_amd/csrc/eh_krylov_kernels.h", "paper_2411_15897_amd/csrc/eh_common.h"],
     "fine_sweep": _FINE3, "fine_resid": _FINE3, "fine_first": _FINE3, "coarse": _STENCIL3,
     "restrict": _TRANSFER3, "prolong": _TRANSFER3,
+    "dense": DEFAULT_SOURCES + ["paper_2411_15897_amd/csrc/eh_coarse_kernels.h"],
     "vcycle": _FINE3 + ["paper_2411_15897_amd/csrc/eh_stencil3_kernels.h",
-                        "paper_2411_15897_amd/csrc/eh_transfer3_kernels.h"],
+                        "paper_2411_15897_amd/csrc/eh_transfer3_kernels.h",
+                        "paper_2411_15897_amd/csrc/eh_coarse_kernels.h"],
 }
 
 

@@ -313,126 +313,203 @@ k_stencil_f64(Dims d, Widths w, const c128* __restrict__ st, const c128* __restr
 
 constexpr int BT_MAXS = 4;
 
-// One group step of the forward or back sweep for up to BT_MAXS blocks.
-// Per slot: the group's matrix (F_I or B_I), its rows b and the columns
-// coupling to the neighbour group bo, the group's entries of the point
-// permutation, the FP64 work vector (group order, stride ldy per
-// right-hand side) at this group (y) and at the neighbour group (yo), and
-// the level's vectors in the multigrid precision (f in, e out).
+// Block-tridiagonal solve of X x = f over the groups I of a partition,
+// with S_I the Schur complements, L_I / U_I the couplings to groups I - 1 /
+// I + 1, F_I = [S_I^-1 | -S_I^-1 L_I] and B_I = -S_I^-1 U_I:
+//   forward  y_I = S_I^-1 f_I + (-S_I^-1 L_I) y_{I-1}
+//   back     x_I = y_I + B_I x_{I+1}.
+// The first term of the forward sweep does not depend on the sweep, so one
+// launch computes it for every group (k_bt_fpart); the sweeps then add, one
+// group step per launch, a matrix-vector product with the neighbour
+// group's vector in place (k_bt_chain).  Products and sums in FP64.
+
+// Both are matrix-vector products whose vector a group of rows shares: one
+// row per wavefront, four per workgroup.  Per chunk of columns each
+// wavefront first issues all loads of its row's entries, the workgroup
+// stages the vector's chunk (every right-hand side, FP64) in LDS, and each
+// lane sums its columns in a fixed order; a butterfly over the wavefront's
+// lanes completes the row.  The arithmetic of a right-hand side does not
+// depend on the others in the chunk.
+// columns per lane and chunk (the staged chunk holds 40 KB at most)
+template <int RB>
+constexpr int bt_na() { return RB >= 8 ? 5 : 10; }
+constexpr int BT_RW = 4;                // rows per workgroup, one per wavefront
+
+template <int RB>
+__device__ __forceinline__ void bt_wave_sum(double (&ar)[RB], double (&ai)[RB]) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        for (int off = 32; off > 0; off >>= 1) {
+            ar[r] += __shfl_xor(ar[r], off, 64);
+            ai[r] += __shfl_xor(ai[r], off, 64);
+        }
+}
+
+// Accumulate this wavefront's row A (nc entries; null: no row) times the
+// staged vectors, chunk by chunk; stage(c0, w, xs) writes columns c0 ..
+// c0 + w - 1 of every right-hand side into xs[r * CW + cc], CW = 64 NA.
+template <int RB, class Stage>
+__device__ __forceinline__ void bt_rows(const c128* __restrict__ A, int nc, c128* xs, Stage stage,
+                                        double (&ar)[RB], double (&ai)[RB]) {
+    constexpr int NA = bt_na<RB>(), CW = 64 * NA;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) { ar[r] = 0.0; ai[r] = 0.0; }
+    for (int c0 = 0; c0 < nc; c0 += CW) {
+        const int w = min(CW, nc - c0);
+        c128 mv[NA];
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int c = lane + 64 * u;
+            mv[u] = (A && c < w) ? A[c0 + c] : mk(0.0, 0.0);
+        }
+        stage(c0, w, xs);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int c = lane + 64 * u;
+            if (c < w) {
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const c128 x = xs[r * CW + c];
+                    ar[r] += mv[u].re * x.re - mv[u].im * x.im;
+                    ai[r] += mv[u].re * x.im + mv[u].im * x.re;
+                }
+            }
+        }
+        if (c0 + CW < nc) __syncthreads();   // the next chunk reuses xs
+    }
+    bt_wave_sum<RB>(ar, ai);
+}
+
+// Every group's S_I^-1 f_I.  Per slot: N points, groups of b0 rows (the
+// last may be shorter), nb groups, F_I at mats + offF[I] with rows of b_I +
+// b_{I-1} entries, the point permutation in group order, the FP64 work
+// vector y (stride N per right-hand side) and f in the level's layout.
+template <class T>
+struct BTAll {
+    int ns;
+    int nrhs;
+    int N[BT_MAXS], b0[BT_MAXS], nb[BT_MAXS];
+    const c128* mats[BT_MAXS];
+    const int64_t* offF[BT_MAXS];   // device array, one entry per group
+    const int* perm[BT_MAXS];
+    c128* y[BT_MAXS];
+    const cplx<T>* f[BT_MAXS];
+    int64_t vf[BT_MAXS];
+};
+
+// Grid (row blocks of BT_RW of the largest group, groups x slots (slot
+// fastest), chunks of RB right-hand sides).
+template <class T, int RB>
+__global__ void __launch_bounds__(256)
+k_bt_fpart(BTAll<T> a) {
+    constexpr int CW = 64 * bt_na<RB>();
+    __shared__ c128 xs[RB * CW];
+    const int s = blockIdx.y % a.ns, I = blockIdx.y / a.ns;
+    if (I >= a.nb[s]) return;
+    const int N = a.N[s], b0 = a.b0[s];
+    const int b = min(b0, N - I * b0), bprev = I > 0 ? b0 : 0;
+    const int row0 = blockIdx.x * BT_RW;
+    if (row0 >= b) return;
+    const int row = row0 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const c128* A = row < b ? a.mats[s] + a.offF[s][I] + (int64_t)row * (b + bprev) : nullptr;
+    const int* perm = a.perm[s] + (int64_t)I * b0;
+    const int r0 = blockIdx.z * RB;
+    const int cnt = min(RB, a.nrhs - r0);
+    const int64_t vf = a.vf[s];
+    const cplx<T>* f = a.f[s] + (int64_t)r0 * vf;
+    auto stage = [&](int c0, int w, c128* x) {
+        constexpr int K = (CW + 255) / 256;
+        int pc[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int cc = threadIdx.x + 256 * k;
+            pc[k] = cc < w ? perm[c0 + cc] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int cc = threadIdx.x + 256 * k;
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (cc < w) {
+                    const cplx<T> v = r < cnt ? f[r * vf + pc[k]] : czero<T>();
+                    x[r * CW + cc] = mk(double(v.re), double(v.im));
+                }
+        }
+    };
+    double ar[RB], ai[RB];
+    bt_rows<RB>(A, b, xs, stage, ar, ai);
+    if (row < b) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (lane == r && r < cnt) a.y[s][(int64_t)(r0 + r) * N + (int64_t)I * b0 + row] = mk(ar[r], ai[r]);
+    }
+}
+
+// One group step of a sweep for up to BT_MAXS blocks.  Per slot: the rows b
+// of the group's matrix (the coupling columns -S_I^-1 L_I of F_I, or B_I),
+// its row stride lda, the columns bo (the neighbour group's size), the
+// group's entries of the point permutation, the work vector at this group
+// (y) and at the neighbour group (yo), stride ldy per right-hand side, and
+// (back sweep) the level's vector e in the multigrid precision.
 template <class T>
 struct BTStep {
     int ns;
     int nrhs;
     const c128* mat[BT_MAXS];
-    int b[BT_MAXS], bo[BT_MAXS];
+    int b[BT_MAXS], bo[BT_MAXS], lda[BT_MAXS];
     const int* perm[BT_MAXS];
     c128* y[BT_MAXS];
     const c128* yo[BT_MAXS];
     int64_t ldy[BT_MAXS];
-    const cplx<T>* f[BT_MAXS];
     cplx<T>* e[BT_MAXS];
-    int64_t vf[BT_MAXS], ve[BT_MAXS];
+    int64_t ve[BT_MAXS];
 };
 
-// Fixed-order sum of RB complex accumulators over the 256 threads; thread r
-// < RB receives entry r.
-template <int RB>
-__device__ __forceinline__ void bt_reduce(double (&ar)[RB], double (&ai)[RB]) {
-    __shared__ double sr[4][RB], si[4][RB];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// y_I += M yo, in place; the back sweep also writes e = x_I in the level's
+// layout and precision.  Grid (row blocks of BT_RW, slots, chunks of RB
+// right-hand sides).
+template <class T, int RB, bool BACK>
+__global__ void __launch_bounds__(256)
+k_bt_chain(BTStep<T> a) {
+    constexpr int CW = 64 * bt_na<RB>();
+    __shared__ c128 xs[RB * CW];
+    const int s = blockIdx.y;
+    if (s >= a.ns) return;
+    const int b = a.b[s], bo = a.bo[s];
+    const int row0 = blockIdx.x * BT_RW;
+    if (row0 >= b) return;
+    const int row = row0 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r0 = blockIdx.z * RB;
+    const int cnt = min(RB, a.nrhs - r0);
+    const int64_t ldy = a.ldy[s];
+    // this lane's entry of y (lane r: right-hand side r0 + r), loaded early
+    const bool wr = row < b && lane < cnt;
+    c128* yp = a.y[s] + (wr ? (int64_t)(r0 + lane) * ldy + row : 0);
+    const c128 yv = wr ? *yp : mk(0.0, 0.0);
+    const c128* A = row < b ? a.mat[s] + (int64_t)row * a.lda[s] : nullptr;
+    const c128* xo = a.yo[s] + (int64_t)r0 * ldy;
+    auto stage = [&](int c0, int w, c128* x) {
+        constexpr int K = (CW + 255) / 256;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        for (int off = 32; off > 0; off >>= 1) {
-            ar[r] += __shfl_xor(ar[r], off, 64);
-            ai[r] += __shfl_xor(ai[r], off, 64);
+        for (int k = 0; k < K; ++k) {
+            const int cc = threadIdx.x + 256 * k;
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (cc < w) x[r * CW + cc] = r < cnt ? xo[r * ldy + c0 + cc] : mk(0.0, 0.0);
         }
-        if (lane == 0) { sr[wave][r] = ar[r]; si[wave][r] = ai[r]; }
-    }
-    __syncthreads();
-    if (threadIdx.x < RB) {
-        const int r = threadIdx.x;
-        ar[0] = (sr[0][r] + sr[1][r]) + (sr[2][r] + sr[3][r]);
-        ai[0] = (si[0][r] + si[1][r]) + (si[2][r] + si[3][r]);
-    }
-}
-
-// Forward step: y_I = F_I [f_I; y_{I-1}].  Grid (rows, slots, chunks of RB
-// right-hand sides); one matrix row per workgroup.
-template <class T, int RB>
-__global__ void __launch_bounds__(256)
-k_bt_fwd(BTStep<T> a) {
-    const int s = blockIdx.y;
-    if (s >= a.ns) return;
-    const int row = blockIdx.x, b = a.b[s], bo = a.bo[s];
-    if (row >= b) return;
-    const int r0 = blockIdx.z * RB;
-    const int cnt = min(RB, a.nrhs - r0);
-    const c128* A = a.mat[s] + (int64_t)row * (b + bo);
-    const int* perm = a.perm[s];
-    const cplx<T>* f = a.f[s] + (int64_t)r0 * a.vf[s];
-    const c128* yo = a.yo[s] + (int64_t)r0 * a.ldy[s];
+    };
     double ar[RB], ai[RB];
+    bt_rows<RB>(A, bo, xs, stage, ar, ai);
+    if (!wr) return;
+    double sr = 0.0, si = 0.0;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) { ar[r] = 0.0; ai[r] = 0.0; }
-    for (int c = threadIdx.x; c < b; c += 256) {
-        const c128 m = A[c];
-        const int64_t p = perm[c];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-            if (r < cnt) {
-                const cplx<T> v = f[r * a.vf[s] + p];
-                ar[r] += m.re * double(v.re) - m.im * double(v.im);
-                ai[r] += m.re * double(v.im) + m.im * double(v.re);
-            }
-    }
-    for (int c = threadIdx.x; c < bo; c += 256) {
-        const c128 m = A[b + c];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-            if (r < cnt) {
-                const c128 v = yo[r * a.ldy[s] + c];
-                ar[r] += m.re * v.re - m.im * v.im;
-                ai[r] += m.re * v.im + m.im * v.re;
-            }
-    }
-    bt_reduce<RB>(ar, ai);
-    if (threadIdx.x < cnt) a.y[s][(int64_t)(r0 + threadIdx.x) * a.ldy[s] + row] = mk(ar[0], ai[0]);
-}
-
-// Back step: x_I = y_I + B_I x_{I+1} (in place in the work vector), and
-// e = x_I in the level's layout and precision.
-template <class T, int RB>
-__global__ void __launch_bounds__(256)
-k_bt_back(BTStep<T> a) {
-    const int s = blockIdx.y;
-    if (s >= a.ns) return;
-    const int row = blockIdx.x, b = a.b[s], bo = a.bo[s];
-    if (row >= b) return;
-    const int r0 = blockIdx.z * RB;
-    const int cnt = min(RB, a.nrhs - r0);
-    const c128* A = a.mat[s] + (int64_t)row * bo;
-    const c128* xo = a.yo[s] + (int64_t)r0 * a.ldy[s];
-    double ar[RB], ai[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) { ar[r] = 0.0; ai[r] = 0.0; }
-    for (int c = threadIdx.x; c < bo; c += 256) {
-        const c128 m = A[c];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-            if (r < cnt) {
-                const c128 v = xo[r * a.ldy[s] + c];
-                ar[r] += m.re * v.re - m.im * v.im;
-                ai[r] += m.re * v.im + m.im * v.re;
-            }
-    }
-    bt_reduce<RB>(ar, ai);
-    if (threadIdx.x < cnt) {
-        const int r = r0 + threadIdx.x;
-        c128* yp = a.y[s] + (int64_t)r * a.ldy[s] + row;
-        const c128 x = mk(yp->re + ar[0], yp->im + ai[0]);
-        *yp = x;
-        a.e[s][(int64_t)r * a.ve[s] + a.perm[s][row]] = mk<T>(T(x.re), T(x.im));
-    }
+    for (int r = 0; r < RB; ++r)
+        if (lane == r) { sr = ar[r]; si = ai[r]; }
+    const c128 x = mk(yv.re + sr, yv.im + si);
+    *yp = x;
+    if (BACK) a.e[s][(int64_t)(r0 + lane) * a.ve[s] + a.perm[s][row]] = mk<T>(T(x.re), T(x.im));
 }
 
 }  // namespace eh

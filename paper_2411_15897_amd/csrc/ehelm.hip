@@ -109,6 +109,7 @@ struct BTData {
     std::vector<int64_t> goff;   // first entry of each group in the group order (nb + 1)
     std::vector<int64_t> offF;   // F_I = [S_I^-1 | -S_I^-1 L_I] in mats
     std::vector<int64_t> offB;   // B_I = -S_I^-1 U_I in mats
+    int64_t* offF_d = nullptr;   // offF on the device
     c128* mats = nullptr;
     int* perm = nullptr;         // group order -> point index (N)
     c128* y = nullptr;           // FP64 work vector, nrhs_cap * N
@@ -606,6 +607,8 @@ void build_bt(eh_ctx* c, Block& B, c128* st, const Widths& w, const Dims& d) {
         tot += (int64_t)pt.bsize(I) * pt.bsize(I + 1);
     }
     T.mats = c->alloc<c128>((size_t)tot);
+    T.offF_d = c->alloc<int64_t>((size_t)nb);
+    HIPCHK(hipMemcpy(T.offF_d, T.offF.data(), (size_t)nb * sizeof(int64_t), hipMemcpyHostToDevice));
     {
         std::vector<int> perm((size_t)N);
         for (int I = 0; I < nb; ++I)
@@ -1006,9 +1009,11 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
             void* const* out, const int64_t* vo, bool guess, int nrhs);
 
 // Coarsest solve e = X_c^-1 f for the blocks kinds[0..ns) by the block-
-// tridiagonal factors: forward sweep over the groups, then back sweep, one
-// launch per group step for all blocks of the launch (a block with fewer
-// groups idles in the last steps).  Right-hand sides in chunks of up to 8
+// tridiagonal factors: every group's S_I^-1 f_I in one launch, then the
+// forward sweep over the groups adding -S_I^-1 L_I y_{I-1}, then the back
+// sweep adding B_I x_{I+1}, one launch per group step for all blocks of
+// the launch (a block with fewer groups idles in the last steps; the first
+// forward step has nothing to add).  Right-hand sides in chunks of up to 8
 // per workgroup, each matrix row read once per chunk.
 template <class T>
 void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const int64_t* vf, void* const* out,
@@ -1016,33 +1021,63 @@ void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const i
     if (ns > BT_MAXS) throw ArgError{"internal: too many blocks for one block-tridiagonal launch"};
     const int RB = nrhs >= 5 ? 8 : nrhs >= 3 ? 4 : nrhs;
     const unsigned chunks = (unsigned)((nrhs + RB - 1) / RB);
-    int maxnb = 0;
-    for (int s = 0; s < ns; ++s) maxnb = std::max(maxnb, c->blk[kinds[s]].btd.pt.nb);
-    // algorithmic bytes of one step: the group's matrix rows once per chunk
-    // of right-hand sides, the vector entries read and written once
+    int maxnb = 0, maxb0 = 1;
+    BTAll<T> fa{};
+    fa.ns = ns;
+    fa.nrhs = nrhs;
+    double fby = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        const BTData& bd = c->blk[kinds[s]].btd;
+        const BTPart& pt = bd.pt;
+        maxnb = std::max(maxnb, pt.nb);
+        fa.N[s] = (int)pt.d.np();
+        fa.b0[s] = pt.bsize(0);
+        fa.nb[s] = pt.nb;
+        fa.mats[s] = bd.mats;
+        fa.offF[s] = bd.offF_d;
+        fa.perm[s] = bd.perm;
+        fa.y[s] = bd.y;
+        fa.f[s] = (const cplx<T>*)f[s];
+        fa.vf[s] = vf[s];
+        maxb0 = std::max(maxb0, fa.b0[s]);
+        // algorithmic bytes: the S_I^-1 blocks once per chunk, f read, y written
+        for (int I = 0; I < pt.nb; ++I) fby += (double)pt.bsize(I) * pt.bsize(I) * sizeof(c128) * chunks;
+        fby += (double)fa.N[s] * nrhs * (sizeof(cplx<T>) + sizeof(c128));
+    }
+    {
+        Timed tm(c, KC_DENSE, fby);
+        const dim3 g((unsigned)((maxb0 + BT_RW - 1) / BT_RW), (unsigned)(maxnb * ns), chunks);
+        if (RB == 8) hipLaunchKernelGGL((k_bt_fpart<T, 8>), g, dim3(256), 0, c->s, fa);
+        else if (RB == 4) hipLaunchKernelGGL((k_bt_fpart<T, 4>), g, dim3(256), 0, c->s, fa);
+        else if (RB == 2) hipLaunchKernelGGL((k_bt_fpart<T, 2>), g, dim3(256), 0, c->s, fa);
+        else hipLaunchKernelGGL((k_bt_fpart<T, 1>), g, dim3(256), 0, c->s, fa);
+        HIPCHK(hipGetLastError());
+    }
+    // algorithmic bytes of one step: the matrix rows once per chunk, the
+    // neighbour's vector entries read, this group's read and written (and e
+    // written in the back sweep)
     auto step_bytes = [&](bool fwd, const BTStep<T>& a) {
         double by = 0.0;
         for (int s = 0; s < ns; ++s) {
             const double b = a.b[s], bo = a.bo[s];
-            by += (fwd ? b * (b + bo) : b * bo) * sizeof(c128) * chunks;
-            by += nrhs * (fwd ? b * (sizeof(cplx<T>) + sizeof(c128)) + bo * sizeof(c128)
-                              : b * (sizeof(cplx<T>) + 2.0 * sizeof(c128)) + bo * sizeof(c128));
+            by += b * bo * sizeof(c128) * chunks;
+            by += nrhs * (bo * sizeof(c128) + b * (2.0 * sizeof(c128) + (fwd ? 0.0 : (double)sizeof(cplx<T>))));
         }
         return by;
     };
     auto launch = [&](bool fwd, const BTStep<T>& a, int maxb) {
         Timed tm(c, KC_DENSE, step_bytes(fwd, a));
-        const dim3 g((unsigned)std::max(maxb, 1), (unsigned)ns, chunks);
-#define EH_BT(RBV)                                                                  \
-    if (fwd) hipLaunchKernelGGL((k_bt_fwd<T, RBV>), g, dim3(256), 0, c->s, a);      \
-    else hipLaunchKernelGGL((k_bt_back<T, RBV>), g, dim3(256), 0, c->s, a);
+        const dim3 g((unsigned)((std::max(maxb, 1) + BT_RW - 1) / BT_RW), (unsigned)ns, chunks);
+#define EH_BT(RBV)                                                                          \
+    if (fwd) hipLaunchKernelGGL((k_bt_chain<T, RBV, false>), g, dim3(256), 0, c->s, a);     \
+    else hipLaunchKernelGGL((k_bt_chain<T, RBV, true>), g, dim3(256), 0, c->s, a);
         if (RB == 8) { EH_BT(8) } else if (RB == 4) { EH_BT(4) } else if (RB == 2) { EH_BT(2) } else { EH_BT(1) }
 #undef EH_BT
         HIPCHK(hipGetLastError());
     };
     for (int pass = 0; pass < 2; ++pass) {
         const bool fwd = pass == 0;
-        for (int k = 0; k < maxnb; ++k) {
+        for (int k = fwd ? 1 : 0; k < maxnb; ++k) {
             BTStep<T> a{};
             a.ns = ns;
             a.nrhs = nrhs;
@@ -1050,22 +1085,21 @@ void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const i
             for (int s = 0; s < ns; ++s) {
                 const BTData& bd = c->blk[kinds[s]].btd;
                 const BTPart& pt = bd.pt;
-                const int64_t N = pt.d.np();
-                a.ldy[s] = N;
-                a.f[s] = (const cplx<T>*)f[s];
-                a.vf[s] = vf[s];
+                a.ldy[s] = pt.d.np();
                 a.e[s] = (cplx<T>*)out[s];
                 a.ve[s] = vo[s];
                 const int I = fwd ? k : pt.nb - 1 - k;
                 if (k >= pt.nb) {
-                    a.b[s] = 0; a.bo[s] = 0;
+                    a.b[s] = 0; a.bo[s] = 0; a.lda[s] = 0;
                     a.mat[s] = bd.mats; a.perm[s] = bd.perm; a.y[s] = bd.y; a.yo[s] = bd.y;
                     continue;
                 }
                 const int J = fwd ? I - 1 : I + 1;
                 a.b[s] = pt.bsize(I);
                 a.bo[s] = pt.bsize(J);
-                a.mat[s] = bd.mats + (fwd ? bd.offF[I] : bd.offB[I]);
+                // forward: the coupling columns of F_I (after its b_I columns of S_I^-1)
+                a.lda[s] = fwd ? a.b[s] + a.bo[s] : a.bo[s];
+                a.mat[s] = bd.mats + (fwd ? bd.offF[I] + a.b[s] : bd.offB[I]);
                 a.perm[s] = bd.perm + bd.goff[I];
                 a.y[s] = bd.y + bd.goff[I];
                 a.yo[s] = bd.y + ((J >= 0 && J < pt.nb) ? bd.goff[J] : 0);
