@@ -135,6 +135,33 @@ def test_cycle_with_block_tridiagonal_coarsest(n, intergrid, levels):
     g32.close()
 
 
+@pytest.mark.parametrize("intergrid", ["mixed", "full"])
+def test_wide_groups_batched(intergrid):
+    """Coarsest 20^3: groups of one plane (400-420 unknowns) with the mixed
+    intergrid, plane pairs (800-840) with full weighting, so the forward
+    and back steps and the S_I^-1 f_I launch take their columns in several
+    chunks (320 columns per chunk with 5-8 right-hand sides, 640 with
+    fewer).  Each right-hand side of a batch of 7, and one alone, against
+    the oracle's cycle with splu on the coarsest level (FP64, 1e-10)."""
+    say("block-tridiagonal wide groups, batched", intergrid)
+    n, alpha = (40, 40, 40), 0.3
+    nu, damping = (2, 2), (0.8, 0.8, 0.2)
+    kw = dict(levels=2, alpha=alpha, nu=nu, damping=damping, intergrid=intergrid, coarse_solver="bt")
+    gpu, s = make(n, seed=5, mg_precision=64, **kw)
+    for b in range(4):
+        X = block_op(s, b, alpha)
+        nodal = (False,) * 3 if b == 3 else face_nodal(3, b)
+        mg = Hierarchy(X, s.n, nodal, 2, damping=damping, nu=nu, intergrid=intergrid)
+        f = crand((7, X.shape[0]), 50 + b)
+        e = gpu.block_cycle(b, to_dev(f)).cpu().numpy()
+        e1 = gpu.block_cycle(b, to_dev(f[:1])).cpu().numpy()[0]
+        errs = [rel(e[k], mg(f[k])) for k in range(7)]
+        say(f"  block {b}: max rel err {max(errs):.1e}")
+        assert max(errs) <= 1e-10, (b, errs)
+        assert rel(e1, e[0]) <= 1e-13
+    gpu.close()
+
+
 @pytest.mark.parametrize("nrhs", [3, 7, 9])
 def test_batch_equals_single(nrhs):
     """Chunks of 4 or 8 right-hand sides per workgroup (and a ragged last

@@ -289,6 +289,40 @@ def test_mixed_intergrid_levels_and_cycle_fp64(n, levels):
     gpu.close()
 
 
+@pytest.mark.parametrize("intergrid", ["mixed", "full"])
+def test_3d_cycle_several_tiles_ragged(intergrid):
+    """The plane-staged 3D kernels on grids of several tiles, the last one
+    ragged in x and y on every level (tiles of 32 x 8 points): fine sweeps,
+    residual and first two sweeps (72 x 40 x 20 cells: 3 x 5 tiles, 3 x 6
+    along a nodal y), the 27-point coarse sweeps of the mixed intergrid (36
+    x 20 x 10: 2 x 3 tiles), restriction (coarse tiles) and prolongation
+    (fine tiles).  Every block's V(2,2) cycle against the oracle (FP64,
+    1e-10); complex64 multigrid within 1e-5; a batch of 3 bitwise equal to
+    its right-hand sides alone."""
+    say("3D cycle, several ragged tiles", intergrid)
+    n, levels, alpha = (72, 40, 20), 3, 0.3
+    nu, damping = (2, 2), (0.8, 0.8, 0.2)
+    kw = dict(levels=levels, alpha=alpha, nu=nu, damping=damping, intergrid=intergrid)
+    g64, s = make(n, seed=31, mg_precision=64, **kw)
+    g32, _ = make(n, seed=31, mg_precision=32, **kw)
+    for b in range(4):
+        X = s.H_p(alpha) if b == 3 else s.A_block(b, alpha)
+        nodal = (False,) * 3 if b == 3 else face_nodal(3, b)
+        mg = Hierarchy(X, s.n, nodal, levels, damping=damping, nu=nu, intergrid=intergrid)
+        f = crand((3, X.shape[0]), 80 + b)
+        e64 = g64.block_cycle(b, to_dev(f)).cpu().numpy()
+        e32 = g32.block_cycle(b, to_dev(f)).cpu().numpy()
+        for k in range(3):
+            ref = mg(f[k])
+            assert rel(e64[k], ref) <= 1e-10, (b, k, rel(e64[k], ref))
+            assert rel(e32[k], ref) <= 1e-5, (b, k, rel(e32[k], ref))
+            e1 = g32.block_cycle(b, to_dev(f[k:k + 1])).cpu().numpy()[0]
+            assert np.array_equal(e1, e32[k]), (b, k)
+        say(f"  block {b}: FP64 {rel(e64[0], mg(f[0])):.1e}, complex64 {rel(e32[0], mg(f[0])):.1e}")
+    g64.close()
+    g32.close()
+
+
 def test_solve_3d_layered_small():
     """The 3D layered-with-inclusion workload at 24^3 (4 sources, mixed
     intergrid, V(2,2), complex64 multigrid): true residual below 1e-6 as
