@@ -1014,7 +1014,8 @@ void gcycle(eh_ctx* c, const int* kinds, int ns, int l, const void* const* f, co
 // sweep adding B_I x_{I+1}, one launch per group step for all blocks of
 // the launch (a block with fewer groups idles in the last steps; the first
 // forward step has nothing to add).  Right-hand sides in chunks of up to 8
-// per workgroup, each matrix row read once per chunk.
+// per workgroup (the steps of batches up to 4: one), each matrix row read
+// once per chunk.
 template <class T>
 void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const int64_t* vf, void* const* out,
               const int64_t* vo, int nrhs) {
@@ -1053,9 +1054,15 @@ void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const i
         else hipLaunchKernelGGL((k_bt_fpart<T, 1>), g, dim3(256), 0, c->s, fa);
         HIPCHK(hipGetLastError());
     }
-    // algorithmic bytes of one step: the matrix rows once per chunk, the
-    // neighbour's vector entries read, this group's read and written (and e
-    // written in the back sweep)
+    // The sweep steps are latency-bound: up to 4 right-hand sides, one per
+    // workgroup (a shorter chain of work per workgroup, the rows re-read
+    // from the caches) beats reading the rows once for the batch (192^3 x 4:
+    // 111 -> 90 ms per solve).  Algorithmic bytes of one step: the matrix
+    // rows once per chunk of up to 8 right-hand sides, the neighbour's
+    // vector entries read, this group's read and written (and e written in
+    // the back sweep).
+    const int RBc = nrhs <= 4 ? 1 : RB;
+    const unsigned chunksc = (unsigned)((nrhs + RBc - 1) / RBc);
     auto step_bytes = [&](bool fwd, const BTStep<T>& a) {
         double by = 0.0;
         for (int s = 0; s < ns; ++s) {
@@ -1067,11 +1074,11 @@ void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const i
     };
     auto launch = [&](bool fwd, const BTStep<T>& a, int maxb) {
         Timed tm(c, KC_DENSE, step_bytes(fwd, a));
-        const dim3 g((unsigned)((std::max(maxb, 1) + BT_RW - 1) / BT_RW), (unsigned)ns, chunks);
+        const dim3 g((unsigned)((std::max(maxb, 1) + BT_RW - 1) / BT_RW), (unsigned)ns, chunksc);
 #define EH_BT(RBV)                                                                          \
     if (fwd) hipLaunchKernelGGL((k_bt_chain<T, RBV, false>), g, dim3(256), 0, c->s, a);     \
     else hipLaunchKernelGGL((k_bt_chain<T, RBV, true>), g, dim3(256), 0, c->s, a);
-        if (RB == 8) { EH_BT(8) } else if (RB == 4) { EH_BT(4) } else if (RB == 2) { EH_BT(2) } else { EH_BT(1) }
+        if (RBc == 8) { EH_BT(8) } else if (RBc == 4) { EH_BT(4) } else if (RBc == 2) { EH_BT(2) } else { EH_BT(1) }
 #undef EH_BT
         HIPCHK(hipGetLastError());
     };
