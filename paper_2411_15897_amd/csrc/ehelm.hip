@@ -1020,6 +1020,7 @@ template <class T>
 void bt_solve(eh_ctx* c, const int* kinds, int ns, const void* const* f, const int64_t* vf, void* const* out,
               const int64_t* vo, int nrhs) {
     if (ns > BT_MAXS) throw ArgError{"internal: too many blocks for one block-tridiagonal launch"};
+    if (nrhs < 1) return;
     const int RB = nrhs >= 5 ? 8 : nrhs >= 3 ? 4 : nrhs;
     const unsigned chunks = (unsigned)((nrhs + RB - 1) / RB);
     int maxnb = 0, maxb0 = 1;
