@@ -323,6 +323,28 @@ def test_3d_cycle_several_tiles_ragged(intergrid):
     g32.close()
 
 
+@pytest.mark.parametrize("n,intergrid", [((8, 4, 16), "mixed"), ((8, 4, 16), "full"),
+                                         ((64, 8, 8), "mixed"), ((4, 40, 8), "full")])
+def test_3d_cycle_degenerate_levels(n, intergrid):
+    """3D hierarchies with thin levels: a coarsest level one cell high
+    (8 x 4 x 16 -> 2 x 1 x 4: cell-centred interpolation with no neighbour
+    along y), tiles mostly outside the grid, long thin grids along x and
+    y.  Every block's V(2,2) cycle against the oracle (FP64, 1e-10)."""
+    say("3D cycle, degenerate levels", n, intergrid)
+    levels, alpha, nu, damping = 3, 0.3, (2, 2), (0.8, 0.8, 0.2)
+    gpu, s = make(n, seed=37, levels=levels, alpha=alpha, mg_precision=64, nu=nu, damping=damping,
+                  intergrid=intergrid)
+    for b in range(4):
+        X = s.H_p(alpha) if b == 3 else s.A_block(b, alpha)
+        nodal = (False,) * 3 if b == 3 else face_nodal(3, b)
+        mg = Hierarchy(X, s.n, nodal, levels, damping=damping, nu=nu, intergrid=intergrid)
+        f = crand((2, X.shape[0]), 90 + b)
+        e = gpu.block_cycle(b, to_dev(f)).cpu().numpy()
+        for k in range(2):
+            assert rel(e[k], mg(f[k])) <= 1e-10, (b, k, rel(e[k], mg(f[k])))
+    gpu.close()
+
+
 def test_solve_3d_layered_small():
     """The 3D layered-with-inclusion workload at 24^3 (4 sources, mixed
     intergrid, V(2,2), complex64 multigrid): true residual below 1e-6 as
