@@ -924,15 +924,16 @@ void gsweep(eh_ctx* c, GArgs<T>& a, int l, int mode, int nrhs) {
                                                                   : (mode == 1 ? KC_FINE_SWEEP : KC_FINE_RESID));
     Timed tm(c, cls, by);
     if (l == 0 && c->dim == 3 && (mode == 1 || mode == 2 || mode == 5)) {
-        // the plane-staged kernel: FTX x FTY tiles of 256 threads
+        // the plane-staged kernel: FTX x FTY tiles of two planes, 256 threads
         int gx = 1, gy = 1;
         for (int s = 0; s < a.ns; ++s) {
             gx = std::max(gx, (a.d[s].g[0] + FTX - 1) / FTX);
             gy = std::max(gy, (a.d[s].g[1] + FTY - 1) / FTY);
         }
-        const int rch = rhs_chunk(gx * gy * a.maxg2, a.ns, nrhs);
+        const int nzb = (a.maxg2 + 1) / 2;   // plane pairs
+        const int rch = rhs_chunk(gx * gy * nzb, a.ns, nrhs);
         const int nch = (std::max(nrhs, 1) + rch - 1) / rch;
-        const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)(a.maxg2 * a.ns * nch));
+        const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)(nzb * a.ns * nch));
 #define EH_G3(KIND)                                                                                              \
     if (mode == 1) hipLaunchKernelGGL((k_gfine3_lds<T, KIND, 1>), g, dim3(256), 0, c->s, a, nrhs, rch);          \
     else if (mode == 2) hipLaunchKernelGGL((k_gfine3_lds<T, KIND, 2>), g, dim3(256), 0, c->s, a, nrhs, rch);     \
