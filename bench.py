@@ -142,11 +142,11 @@ TIMER_GROUPS = {"vcycle": VCYCLE_CLASSES}
 # fixed-order reduction).
 def _gfine(*modes):
     """Kernel names of the fine-level sweeps of the given modes (per point,
-    and plane-staged in 3D)."""
+    and plane-staged in 3D, which has modes 1, 2 and 5)."""
     return (tuple(f"eh::k_gfine<{t}, {k}, {d}, {m}>" for m in modes for t in ("float", "double")
                   for k in (0, 1, 2) for d in (2, 3))
-            + tuple(f"eh::k_gfine3_lds<{t}, {k}, {m}>" for m in modes for t in ("float", "double")
-                    for k in (0, 1, 2)))
+            + tuple(f"eh::k_gfine3_lds<{t}, {k}, {m}>" for m in modes if m in (1, 2, 5)
+                    for t in ("float", "double") for k in (0, 1, 2)))
 
 
 CLASS_KERNELS = {
