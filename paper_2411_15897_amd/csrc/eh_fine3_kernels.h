@@ -10,7 +10,9 @@
 // above, k0 + 1 the plane below) and the other (k0 - 1, k0 + 2) straight
 // from memory; the next right-hand side's values are loaded while this one
 // is computed: one barrier per right-hand side.  The points' couplings,
-// diagonals and first-sweep factors are held for the whole batch.
+// diagonals and first-sweep factors are held for the whole batch; in mode
+// 5 the neighbours' w / D come from both planes' boxes, computed once per
+// launch into LDS.
 // Arithmetic per point (fixed-order fused multiply-adds; the diagonal of a
 // Jacobi update cancels algebraically):
 //   mode 1:  (1 - w) u + w D^-1 (f + s(u))
@@ -73,8 +75,25 @@ k_gfine3_lds(GArgs<T> a, int nrhs, int rch) {
         const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
         sxy[it] = (q < NS && gx >= 0 && gx < d.g[0] && gy >= 0 && gy < d.g[1]) ? (int64_t)gy * sy + gx : -1;
     }
+    const int lu = (ty + 1) * UW + (tx + 1);    // the point in its plane's box
     const cplx<T>* __restrict__ D = a.D[slot];
     const T damp = a.damp, omw = T(1) - damp;
+    // mode 5: w / D over both planes' boxes, once per launch, for the
+    // neighbours' first-sweep factors
+    __shared__ cplx<T> wd[2][MODE == 5 ? NS : 1];
+    if (MODE == 5) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int it = 0; it < NR; ++it) {
+                const int q = tid + it * 256;
+                if (q < NS)
+                    wd[h][q] = (sxy[it] >= 0 && (h == 0 || pl1))
+                                   ? cdiv(mk<T>(damp, T(0)), D[(int64_t)(k0 + h) * sz + sxy[it]])
+                                   : czero<T>();
+            }
+        __syncthreads();
+    }
     cplx<T> Dp[2], sc[2];
     FineCoef<T, KIND, 3> c[2];
     cplx<T> cw[2][6];
@@ -93,11 +112,15 @@ k_gfine3_lds(GArgs<T> a, int nrhs, int rch) {
             const int k = k0 + h;
             const bool nb[6] = {mine[h] && i > 0, mine[h] && i + 1 < d.g[0], mine[h] && j > 0,
                                 mine[h] && j + 1 < d.g[1], mine[h] && k > 0, mine[h] && k + 1 < d.g[2]};
-            const int64_t off[6] = {-1, 1, -sy, sy, -sz, sz};
             const T cc[6] = {c[h].cm[0], c[h].cp[0], c[h].cm[1], c[h].cp[1], c[h].cm[2], c[h].cp[2]};
+            // w / D of the six neighbours: the own plane's box, the other
+            // plane's point, and the outer plane from memory
+            const bool outer = h == 0 ? nb[4] : nb[5];
+            const cplx<T> wo = outer ? cdiv(mk<T>(damp, T(0)), D[h == 0 ? p[0] - sz : p[1] + sz]) : czero<T>();
+            const cplx<T> wn[6] = {wd[h][lu - 1], wd[h][lu + 1], wd[h][lu - UW], wd[h][lu + UW],
+                                   h == 0 ? wo : wd[0][lu], h == 0 ? wd[1][lu] : wo};
 #pragma unroll
-            for (int t = 0; t < 6; ++t)
-                cw[h][t] = nb[t] ? cc[t] * cdiv(mk<T>(damp, T(0)), D[p[h] + off[t]]) : czero<T>();
+            for (int t = 0; t < 6; ++t) cw[h][t] = nb[t] ? cc[t] * wn[t] : czero<T>();
         }
     }
     const bool zm0 = mine[0] && k0 > 0, zp1 = mine[1] && k0 + 2 < d.g[2];
@@ -107,7 +130,6 @@ k_gfine3_lds(GArgs<T> a, int nrhs, int rch) {
     const int64_t vf = a.vf[slot];
     cplx<T>* __restrict__ out = a.out[slot];
     const int64_t vo = a.vo[slot];
-    const int lu = (ty + 1) * UW + (tx + 1);
     cplx<T> vin[2][NR], vzm, vzp, vff[2];
     auto load_in = [&](int r) {
         const cplx<T>* sr = src + (int64_t)r * vsrc;
